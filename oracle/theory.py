@@ -1,0 +1,57 @@
+"""Closed-form results the oracle is checked against.
+
+TEST INFRASTRUCTURE ONLY.  Each function states the textbook result or the
+paper passage it writes out.
+"""
+from __future__ import annotations
+
+import math
+
+
+def duct_resistance_coefficient(h_over_w, terms=50):
+    """Bracketed factor of the rectangular-duct Poiseuille pressure drop
+    (Sec. III.A, Eq. 21): [1 - sum_n 192/((2n+1)^5 pi^5) (h/w)
+    tanh((2n+1) pi w / (2h))]^-1, h and w the half-height and half-width."""
+    s = 0.0
+    for n in range(terms):
+        k = 2 * n + 1
+        s += 192.0 / (k ** 5 * math.pi ** 5) * h_over_w * math.tanh(k * math.pi / (2.0 * h_over_w))
+    return 1.0 / (1.0 - s)
+
+
+def washburn_2d(t, z0, L, H, sigma, theta_deg, mu1, mu2, dP=0.0):
+    """Interface position of the 2D capillary intrusion (Sec. III.C, Eqs. 25-26):
+    the positive root of (mu1-mu2)/2 z^2 + mu2 L z - (sigma cos(theta) H/6 +
+    dP H^2/12) t - (mu1-mu2)/2 z0^2 - mu2 L z0 = 0."""
+    a = 0.5 * (mu1 - mu2)
+    b = mu2 * L
+    drive = sigma * math.cos(math.radians(theta_deg)) * H / 6.0 + dP * H * H / 12.0
+    c = -drive * t - a * z0 * z0 - b * z0
+    if abs(a) < 1e-300:
+        return -c / b
+    return (-b + math.sqrt(b * b - 4.0 * a * c)) / (2.0 * a)
+
+
+def laplace_pressure(sigma, R, dim=3):
+    """Young-Laplace jump across a static interface of radius R: 2 sigma / R
+    for a sphere, sigma / R for a cylinder."""
+    return (2.0 if dim == 3 else 1.0) * sigma / R
+
+
+def poiseuille_profile(y, y0, y1, force, rho, nu):
+    """Plane Poiseuille flow between walls at y0 and y1 driven by a body force
+    per unit volume: u(y) = F/(2 rho nu) (y - y0)(y1 - y)."""
+    return force / (2.0 * rho * nu) * (y - y0) * (y1 - y)
+
+
+def taylor_green_decay(nu, k, t):
+    """Amplitude factor of a 2D Taylor-Green vortex of wavenumber k in both
+    directions: exp(-2 nu k^2 t)."""
+    return math.exp(-2.0 * nu * k * k * t)
+
+
+def cap_angle_from_circle(zc, R, z_wall):
+    """Contact angle (through the liquid inside the circle) of a circular cap
+    whose circle has centre height zc and radius R over a wall plane z_wall."""
+    c = (z_wall - zc) / R
+    return math.degrees(math.acos(max(-1.0, min(1.0, c))))
