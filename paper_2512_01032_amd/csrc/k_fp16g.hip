@@ -1,0 +1,22 @@
+// k_fp16g.hip -- kernel instantiations for one storage mode
+// (compute float, h stored as float, g stored as _Float16).
+#include "kernels_impl.hpp"
+
+namespace pflbm {
+
+hipError_t launch_sweep_fp16g(int mode, int tx, int parity, Desc* d, const Tile* tiles, int ntiles,
+                          int diag, ReadOut ro, InitIn in, hipStream_t s) {
+    return launch_sweep_storage<float, float, _Float16>(mode, tx, parity, d, tiles, ntiles, diag, ro, in, s);
+}
+
+hipError_t launch_phi_fp16g(int parity, const Desc* d, const Tile* tiles, int ntiles, hipStream_t s,
+                        int force) {
+    return launch_phi_storage<float, float>(parity, d, tiles, ntiles, s, force);
+}
+
+hipError_t launch_restore_fp16g(int parity, const Desc* d, const Tile* tiles, int ntiles,
+                            const double* pops, hipStream_t s) {
+    return launch_restore_storage<float, float, _Float16>(parity, d, tiles, ntiles, pops, s);
+}
+
+}  // namespace pflbm

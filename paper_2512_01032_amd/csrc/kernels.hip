@@ -1,0 +1,57 @@
+// kernels.hip -- storage-mode dispatch of the kernel launchers.  The kernels
+// themselves live in kernels_impl.hpp; one translation unit per storage mode
+// (k_fp64, k_fp32, k_fp16g, k_fp16a) instantiates them.
+#include "pflbm.hpp"
+
+namespace pflbm {
+
+hipError_t launch_sweep_fp64(int, int, int, Desc*, const Tile*, int, int, ReadOut, InitIn, hipStream_t);
+hipError_t launch_phi_fp64(int, const Desc*, const Tile*, int, hipStream_t, int);
+hipError_t launch_restore_fp64(int, const Desc*, const Tile*, int, const double*, hipStream_t);
+hipError_t launch_sweep_fp32(int, int, int, Desc*, const Tile*, int, int, ReadOut, InitIn, hipStream_t);
+hipError_t launch_phi_fp32(int, const Desc*, const Tile*, int, hipStream_t, int);
+hipError_t launch_restore_fp32(int, const Desc*, const Tile*, int, const double*, hipStream_t);
+hipError_t launch_sweep_fp16g(int, int, int, Desc*, const Tile*, int, int, ReadOut, InitIn, hipStream_t);
+hipError_t launch_phi_fp16g(int, const Desc*, const Tile*, int, hipStream_t, int);
+hipError_t launch_restore_fp16g(int, const Desc*, const Tile*, int, const double*, hipStream_t);
+hipError_t launch_sweep_fp16a(int, int, int, Desc*, const Tile*, int, int, ReadOut, InitIn, hipStream_t);
+hipError_t launch_phi_fp16a(int, const Desc*, const Tile*, int, hipStream_t, int);
+hipError_t launch_restore_fp16a(int, const Desc*, const Tile*, int, const double*, hipStream_t);
+
+hipError_t launch_sweep(int storage, int mode, int tx, int parity, Desc* d, const Tile* tiles,
+                        int ntiles, int diag, ReadOut ro, InitIn in, hipStream_t s) {
+    switch (storage) {
+        case ST_FP64: return launch_sweep_fp64(mode, tx, parity, d, tiles, ntiles, diag, ro, in, s);
+        case ST_FP32:
+        case ST_FP32_SHIFT: return launch_sweep_fp32(mode, tx, parity, d, tiles, ntiles, diag, ro, in, s);
+        case ST_FP16_G: return launch_sweep_fp16g(mode, tx, parity, d, tiles, ntiles, diag, ro, in, s);
+        case ST_FP16_ALL: return launch_sweep_fp16a(mode, tx, parity, d, tiles, ntiles, diag, ro, in, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_phi(int storage, int parity, const Desc* d, const Tile* tiles, int ntiles,
+                      hipStream_t s, int force) {
+    switch (storage) {
+        case ST_FP64: return launch_phi_fp64(parity, d, tiles, ntiles, s, force);
+        case ST_FP32:
+        case ST_FP32_SHIFT: return launch_phi_fp32(parity, d, tiles, ntiles, s, force);
+        case ST_FP16_G: return launch_phi_fp16g(parity, d, tiles, ntiles, s, force);
+        case ST_FP16_ALL: return launch_phi_fp16a(parity, d, tiles, ntiles, s, force);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_restore(int storage, int parity, const Desc* d, const Tile* tiles, int ntiles,
+                          const double* pops, hipStream_t s) {
+    switch (storage) {
+        case ST_FP64: return launch_restore_fp64(parity, d, tiles, ntiles, pops, s);
+        case ST_FP32:
+        case ST_FP32_SHIFT: return launch_restore_fp32(parity, d, tiles, ntiles, pops, s);
+        case ST_FP16_G: return launch_restore_fp16g(parity, d, tiles, ntiles, pops, s);
+        case ST_FP16_ALL: return launch_restore_fp16a(parity, d, tiles, ntiles, pops, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace pflbm

@@ -1,0 +1,411 @@
+// lattice_host.hip -- validation, classification, tile table and
+// initialisation of one lattice (see lattice_host.hpp).
+#include "lattice_host.hpp"
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+
+namespace pflbm {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+}  // namespace pflbm
+
+extern "C" const char* lbm_last_error(void) { return pflbm::g_err; }
+
+namespace pflbm {
+
+static const int HCX[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+static const int HCY[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+static const int HCZ[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+void storage_sizes(int storage, int* sh, int* sg, int* sphi) {
+    switch (storage) {
+        case ST_FP64: *sh = 8; *sg = 8; *sphi = 8; break;
+        case ST_FP32:
+        case ST_FP32_SHIFT: *sh = 4; *sg = 4; *sphi = 4; break;
+        case ST_FP16_G: *sh = 4; *sg = 2; *sphi = 4; break;
+        default: *sh = 2; *sg = 2; *sphi = 4; break;
+    }
+}
+
+int validate_params(const lbm_params* p, const lbm_geometry* geo) {
+    if (!p) { set_error("params is NULL"); return LBM_E_INVAL; }
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1) {
+        set_error("lattice size %d x %d x %d: every dimension must be >= 1", p->nx, p->ny, p->nz);
+        return LBM_E_INVAL;
+    }
+    const int64_t N = (int64_t)p->nx * p->ny * p->nz;
+    if (N >= ((int64_t)1 << 31)) { set_error("lattice of %lld nodes exceeds 2^31", (long long)N); return LBM_E_INVAL; }
+    if (p->storage < ST_FP64 || p->storage > ST_FP16_ALL) { set_error("unknown storage mode %d", p->storage); return LBM_E_INVAL; }
+    {
+        // every buffer resource spans at most 10 directions and 4 GiB
+        int sh, sg, sphi;
+        storage_sizes(p->storage, &sh, &sg, &sphi);
+        const int64_t big = (int64_t)10 * N * std::max(sh, sg);
+        if (big >= ((int64_t)1 << 32)) {
+            set_error("lattice of %lld nodes: 10 population directions exceed 4 GiB in this storage mode",
+                      (long long)N);
+            return LBM_E_INVAL;
+        }
+    }
+    if (!(p->rho_l > 0) || !(p->rho_g > 0)) { set_error("densities must be > 0"); return LBM_E_INVAL; }
+    if (!(p->nu_l > 0) || !(p->nu_g > 0)) { set_error("viscosities must be > 0 (tau > 1/2)"); return LBM_E_INVAL; }
+    if (!(p->W > 0)) { set_error("interface width W must be > 0"); return LBM_E_INVAL; }
+    if (!(p->M > 0)) { set_error("mobility M must be > 0"); return LBM_E_INVAL; }
+    if (!(p->sigma >= 0)) { set_error("surface tension must be >= 0"); return LBM_E_INVAL; }
+    if (!(p->eps > 0)) { set_error("eps must be > 0"); return LBM_E_INVAL; }
+    if (p->mobility_corr && !(p->mc_D > 0)) { set_error("mobility correction needs D > 0"); return LBM_E_INVAL; }
+    if (p->mix == LBM_MIX_TANH && !(p->mix_width > 0)) { set_error("mix_width must be > 0"); return LBM_E_INVAL; }
+    if (p->mix != LBM_MIX_LINEAR && p->mix != LBM_MIX_TANH) { set_error("unknown mix %d", p->mix); return LBM_E_INVAL; }
+    if (p->friction != LBM_FRICTION_NOSLIP && p->friction != LBM_FRICTION_INTERFACE_SLIP) {
+        set_error("unknown friction %d", p->friction); return LBM_E_INVAL;
+    }
+    const int dims[3] = {p->nx, p->ny, p->nz};
+    for (int f = 0; f < 6; ++f) {
+        if (p->face_bc[f] != LBM_BC_PERIODIC && p->face_bc[f] != LBM_BC_PRESSURE) {
+            set_error("face %d: unknown boundary type %d", f, p->face_bc[f]); return LBM_E_INVAL;
+        }
+        if (p->face_bc[f] == LBM_BC_PRESSURE && dims[f / 2] < 3) {
+            set_error("face %d: a pressure face needs >= 3 nodes along its axis", f); return LBM_E_INVAL;
+        }
+    }
+    if (geo) {
+        for (int k = 0; k < 16; ++k)
+            if (!(geo->theta_deg[k] > 0.0 && geo->theta_deg[k] < 180.0)) {
+                set_error("contact angle of material %d must lie in (0, 180) degrees", k);
+                return LBM_E_INVAL;
+            }
+    }
+    return LBM_OK;
+}
+
+int choose_tx(int nx) {
+    int best = 64, waste_best = 1 << 30;
+    for (int tx : {64, 32, 16}) {
+        const int waste = ((nx + tx - 1) / tx) * tx - nx;
+        if (waste < waste_best) { waste_best = waste; best = tx; }
+    }
+    return best;
+}
+
+int choose_tz(const lbm_params* p, int tx) {
+    const char* env = getenv("LBM_TILE_Z");
+    if (env && atoi(env) > 0) return std::min(atoi(env), p->nz);
+    const int ty = NTHREADS / tx;
+    const int64_t cols = (int64_t)((p->nx + tx - 1) / tx) * ((p->ny + ty - 1) / ty);
+    // deepest chunk that still gives >= 8 tiles per compute unit (256 CUs)
+    int tz = 64;
+    while (tz > 4 && cols * ((p->nz + tz - 1) / tz) < 2048) tz /= 2;
+    return std::min(tz, p->nz);
+}
+
+static void layout_offsets(const lbm_params* p, int64_t ntiles, LatticeLayout* L) {
+    int sh, sg, sphi;
+    storage_sizes(p->storage, &sh, &sg, &sphi);
+    const int64_t N = L->N;
+    size_t o = 0;
+    L->off_desc = o; o = align256(o + sizeof(Desc));
+    L->off_counter = o; o = align256(o + sizeof(unsigned int));
+    L->off_h = o; o = align256(o + (size_t)QH * N * sh);
+    L->off_g = o; o = align256(o + (size_t)QG * N * sg);
+    L->off_phi = o; o = align256(o + (size_t)N * sphi);
+    L->off_flag = o; o = align256(o + (size_t)N);
+    L->off_link = o; o = align256(o + (size_t)N * 4);
+    L->off_tiles = o; o = align256(o + (size_t)ntiles * sizeof(Tile));
+    L->off_partials = o; o = align256(o + (size_t)ntiles * NPART * sizeof(double));
+    L->total = o;
+}
+
+size_t footprint_bytes(const lbm_params* p) {
+    if (validate_params(p, nullptr) != LBM_OK) return 0;
+    LatticeLayout L;
+    L.N = (int64_t)p->nx * p->ny * p->nz;
+    const int tx = choose_tx(p->nx), ty = NTHREADS / tx, tz = choose_tz(p, tx);
+    const int64_t ntiles = (int64_t)((p->nx + tx - 1) / tx) * ((p->ny + ty - 1) / ty) *
+                           ((p->nz + tz - 1) / tz);
+    layout_offsets(p, ntiles, &L);
+    return L.total;
+}
+
+int build_layout(const lbm_params* p, const lbm_geometry* geo, int lat, LatticeLayout* L) {
+    int rc = validate_params(p, geo);
+    if (rc != LBM_OK) return rc;
+    const int nx = p->nx, ny = p->ny, nz = p->nz;
+    const int64_t N = (int64_t)nx * ny * nz;
+    L->N = N;
+    L->flag.assign(N, 0);
+    L->link.assign(N, 0);
+    const uint8_t* solid = geo ? geo->solid : nullptr;
+    auto idx = [&](int x, int y, int z) -> int64_t {
+        x = ((x % nx) + nx) % nx; y = ((y % ny) + ny) % ny; z = ((z % nz) + nz) % nz;
+        return x + (int64_t)nx * (y + (int64_t)ny * z);
+    };
+    int64_t nf = 0, ng = 0, ns = 0;
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const int64_t n = x + (int64_t)nx * (y + (int64_t)ny * z);
+                if (solid && solid[n]) {
+                    if (solid[n] > 16) { set_error("node %lld: material id %d > 16", (long long)n, solid[n]); return LBM_E_INVAL; }
+                    L->flag[n] = make_flag(KIND_SOLID, solid[n] - 1);
+                    ++ns;
+                    continue;
+                }
+                const int c[3] = {x, y, z}, d[3] = {nx, ny, nz};
+                int face = -1, count = 0;
+                for (int f = 0; f < 6; ++f) {
+                    if (p->face_bc[f] != LBM_BC_PRESSURE) continue;
+                    const int layer = (f & 1) ? d[f / 2] - 1 : 0;
+                    if (c[f / 2] == layer) { face = f; ++count; }
+                }
+                if (count > 1) {
+                    set_error("node (%d,%d,%d) lies on two pressure faces; make it solid", x, y, z);
+                    return LBM_E_INVAL;
+                }
+                if (count == 1) { L->flag[n] = make_flag(KIND_GHOST, face); ++ng; }
+                else { L->flag[n] = make_flag(KIND_FLUID, 0); ++nf; }
+            }
+    L->n_fluid = nf; L->n_ghost = ng; L->n_solid = ns;
+    // ghost owners
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const int64_t n = x + (int64_t)nx * (y + (int64_t)ny * z);
+                if (flag_kind(L->flag[n]) != KIND_GHOST) continue;
+                const int face = flag_sub(L->flag[n]);
+                const int ax = face / 2, sg = (face & 1) ? -1 : 1;
+                const int64_t o = idx(x + (ax == 0 ? sg : 0), y + (ax == 1 ? sg : 0), z + (ax == 2 ? sg : 0));
+                if (flag_kind(L->flag[o]) != KIND_FLUID) {
+                    set_error("pressure ghost (%d,%d,%d): its inward neighbour must be fluid", x, y, z);
+                    return LBM_E_INVAL;
+                }
+                L->flag[o] |= F_OWNER;
+                L->link[o] |= 1u << (LINK_OWNER_SHIFT + face);
+            }
+    // solid links of fluid nodes
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const int64_t n = x + (int64_t)nx * (y + (int64_t)ny * z);
+                if (flag_kind(L->flag[n]) != KIND_FLUID) continue;
+                uint32_t m = 0;
+                for (int i = 1; i < 19; ++i)
+                    if (flag_kind(L->flag[idx(x + HCX[i], y + HCY[i], z + HCZ[i])]) == KIND_SOLID) m |= 1u << i;
+                if (m) { L->link[n] |= m; L->flag[n] |= F_NEAR_WALL; }
+            }
+    // tile table: keep tiles holding at least one non-solid node
+    const int tx = choose_tx(nx), ty = NTHREADS / tx, tz = choose_tz(p, tx);
+    L->tx = tx; L->ty = ty; L->tz = tz;
+    L->tiles.clear();
+    for (int z0 = 0; z0 < nz; z0 += tz)
+        for (int y0 = 0; y0 < ny; y0 += ty)
+            for (int x0 = 0; x0 < nx; x0 += tx) {
+                bool any = false;
+                const int z1 = std::min(nz, z0 + tz), y1 = std::min(ny, y0 + ty), x1 = std::min(nx, x0 + tx);
+                for (int z = z0; z < z1 && !any; ++z)
+                    for (int y = y0; y < y1 && !any; ++y)
+                        for (int x = x0; x < x1; ++x)
+                            if (flag_kind(L->flag[x + (int64_t)nx * (y + (int64_t)ny * z)]) != KIND_SOLID) { any = true; break; }
+                if (!any) continue;
+                Tile t;
+                memset(&t, 0, sizeof(t));
+                t.lat = lat; t.x0 = x0; t.y0 = y0; t.z0 = z0; t.zn = z1 - z0;
+                t.tile_in_lat = (int)L->tiles.size();
+                L->tiles.push_back(t);
+            }
+    layout_offsets(p, (int64_t)L->tiles.size(), L);
+    return LBM_OK;
+}
+
+void fill_desc(const lbm_params* p, const lbm_geometry* geo, const LatticeLayout& L, char* base,
+               int64_t step, Desc* d) {
+    memset(d, 0, sizeof(*d));
+    d->nx = p->nx; d->ny = p->ny; d->nz = p->nz; d->tx = L.tx;
+    d->N = L.N;
+    d->storage = p->storage;
+    d->ntiles = (int)L.tiles.size();
+    d->h = base + L.off_h;
+    d->g = base + L.off_g;
+    {
+        int sh, sg, sphi;
+        storage_sizes(p->storage, &sh, &sg, &sphi);
+        for (int q = 0; q < QH; ++q) d->hq[q] = base + L.off_h + (size_t)q * L.N * sh;
+        for (int q = 0; q < QG; ++q) d->gq[q] = base + L.off_g + (size_t)q * L.N * sg;
+    }
+    d->phi = base + L.off_phi;
+    d->flag = (const uint8_t*)(base + L.off_flag);
+    d->link = (const uint32_t*)(base + L.off_link);
+    d->partials = (double*)(base + L.off_partials);
+    d->counter = (unsigned int*)(base + L.off_counter);
+    d->step = step;
+    d->t0 = 0;
+    d->stop_step = INT64_MAX;
+    d->diag_every = p->diag_every > 0 ? p->diag_every : 0;
+    d->rho_l = p->rho_l; d->rho_g = p->rho_g; d->nu_l = p->nu_l; d->nu_g = p->nu_g;
+    d->sigma = p->sigma; d->W = p->W; d->M = p->M;
+    for (int a = 0; a < 3; ++a) d->F[a] = p->F_ex[a];
+    d->mobility_corr = p->mobility_corr ? 1 : 0;
+    d->mix = p->mix; d->friction = p->friction;
+    d->mc_gamma = p->mc_gamma; d->mc_phi_M = p->mc_phi_M; d->mc_phi_m = p->mc_phi_m;
+    d->mc_D = p->mobility_corr ? p->mc_D : 1.0;
+    d->eps = p->eps;
+    d->mix_phi = p->mix_phi; d->mix_width = p->mix == LBM_MIX_TANH ? p->mix_width : 1.0;
+    d->slip_lo = p->slip_lo; d->slip_hi = p->slip_hi;
+    d->P_ref = p->P_ref;
+    for (int f = 0; f < 6; ++f) {
+        d->face_bc[f] = p->face_bc[f];
+        d->face_P[f] = p->face_P[f];
+        d->face_ramp[f] = p->face_ramp[f];
+    }
+    for (int k = 0; k < 16; ++k) {
+        const double th = geo ? geo->theta_deg[k] * M_PI / 180.0 : M_PI / 2;
+        d->cos_t[k] = cos(th);
+        d->sin_t[k] = sin(th);
+    }
+    const bool shifted = p->storage >= ST_FP32_SHIFT;
+    d->clamp_a = p->storage == ST_FP64 ? 1e-12 : 1e-6;
+    d->href = shifted ? 0.5 : 0.0;
+    d->gref = shifted ? p->P_ref * 3.0 : 0.0;
+    const int ksh = p->fp16_log2_scale_h ? p->fp16_log2_scale_h : 3;
+    const int ksg = p->fp16_log2_scale_g ? p->fp16_log2_scale_g : 10;
+    d->scale_h = p->storage == ST_FP16_ALL ? ldexp(1.0, ksh) : 1.0;
+    d->scale_g = p->storage >= ST_FP16_G ? ldexp(1.0, ksg) : 1.0;
+    d->u_max = p->u_max;
+}
+
+#define HIPCHK(expr)                                                              \
+    do {                                                                          \
+        hipError_t e_ = (expr);                                                   \
+        if (e_ != hipSuccess) {                                                   \
+            set_error("%s failed: %s", #expr, hipGetErrorString(e_));             \
+            return LBM_E_DEVICE;                                                  \
+        }                                                                         \
+    } while (0)
+
+int upload_and_init(const lbm_params* p, const lbm_geometry* geo, const lbm_init* init,
+                    LatticeLayout& L, char* base, Desc* hdesc, hipStream_t s) {
+    const int64_t N = L.N;
+    int sh, sg, sphi;
+    storage_sizes(p->storage, &sh, &sg, &sphi);
+    // zero populations and phi (solid slots stay zero), upload geometry
+    HIPCHK(hipMemsetAsync(base + L.off_h, 0, (size_t)QH * N * sh, s));
+    HIPCHK(hipMemsetAsync(base + L.off_g, 0, (size_t)QG * N * sg, s));
+    HIPCHK(hipMemsetAsync(base + L.off_counter, 0, sizeof(unsigned int), s));
+    HIPCHK(hipMemsetAsync(base + L.off_partials, 0, L.tiles.size() * NPART * sizeof(double), s));
+    HIPCHK(hipMemcpyAsync(base + L.off_flag, L.flag.data(), N, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(base + L.off_link, L.link.data(), (size_t)N * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(base + L.off_tiles, L.tiles.data(), L.tiles.size() * sizeof(Tile),
+                          hipMemcpyHostToDevice, s));
+    const int64_t step0 = (init && init->kind == LBM_INIT_POPULATIONS) ? init->step : 0;
+    fill_desc(p, geo, L, base, step0, hdesc);
+    HIPCHK(hipMemcpyAsync(base + L.off_desc, hdesc, sizeof(Desc), hipMemcpyHostToDevice, s));
+    Desc* ddesc = (Desc*)(base + L.off_desc);
+    const Tile* dtiles = (const Tile*)(base + L.off_tiles);
+    const int nt = (int)L.tiles.size();
+    if (!init) { set_error("init is NULL"); return LBM_E_INVAL; }
+    if (init->kind == LBM_INIT_POPULATIONS) {
+        if (!init->pops) { set_error("POPULATIONS init needs pops"); return LBM_E_INVAL; }
+        double* dpops = nullptr;
+        HIPCHK(hipMalloc(&dpops, (size_t)(QH + QG) * N * sizeof(double)));
+        hipError_t e = hipMemcpyAsync(dpops, init->pops, (size_t)(QH + QG) * N * sizeof(double),
+                                      hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = launch_restore(p->storage, (int)(step0 & 1), ddesc, dtiles, nt, dpops, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        hipFree(dpops);
+        if (e != hipSuccess) { set_error("restore: %s", hipGetErrorString(e)); return LBM_E_DEVICE; }
+        return LBM_OK;
+    }
+    if (init->kind != LBM_INIT_FIELDS || !init->phi) {
+        set_error("FIELDS init needs phi"); return LBM_E_INVAL;
+    }
+    // phi: fluid nodes from the input, ghosts from their owners, solid 0
+    std::vector<char> hphi((size_t)N * sphi, 0);
+    const int nx = p->nx, ny = p->ny;
+    for (int64_t n = 0; n < N; ++n) {
+        const int kind = flag_kind(L.flag[n]);
+        double v = 0.0;
+        if (kind == KIND_FLUID) v = init->phi[n];
+        else if (kind == KIND_GHOST) {
+            const int face = flag_sub(L.flag[n]);
+            const int ax = face / 2, sgn = (face & 1) ? -1 : 1;
+            const int64_t stride = ax == 0 ? 1 : (ax == 1 ? nx : (int64_t)nx * ny);
+            v = init->phi[n + sgn * stride];
+        }
+        if (sphi == 8) ((double*)hphi.data())[n] = v;
+        else ((float*)hphi.data())[n] = (float)v;
+    }
+    HIPCHK(hipMemcpyAsync(base + L.off_phi, hphi.data(), hphi.size(), hipMemcpyHostToDevice, s));
+    double *du = nullptr, *dP = nullptr;
+    if (init->u) {
+        HIPCHK(hipMalloc(&du, (size_t)3 * N * sizeof(double)));
+        HIPCHK(hipMemcpyAsync(du, init->u, (size_t)3 * N * sizeof(double), hipMemcpyHostToDevice, s));
+    }
+    if (init->P) {
+        HIPCHK(hipMalloc(&dP, (size_t)N * sizeof(double)));
+        HIPCHK(hipMemcpyAsync(dP, init->P, (size_t)N * sizeof(double), hipMemcpyHostToDevice, s));
+    }
+    ReadOut ro = {nullptr, nullptr, nullptr, nullptr};
+    InitIn in = {du, dP};
+    hipError_t e = launch_sweep(p->storage, MODE_INIT, L.tx, 0, ddesc, dtiles, nt, 0, ro, in, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (du) hipFree(du);
+    if (dP) hipFree(dP);
+    if (e != hipSuccess) { set_error("init kernel: %s", hipGetErrorString(e)); return LBM_E_DEVICE; }
+    return LBM_OK;
+}
+
+int read_lattice(int storage, const Desc& hdesc, int parity, Desc* d_desc, const Tile* d_tiles,
+                 int ntiles, uint32_t mask, double* phi, double* P, double* u, double* pops,
+                 hipStream_t s) {
+    const int64_t N = hdesc.N;
+    const bool want_pop = (mask & (LBM_POP_H | LBM_POP_G)) && pops;
+    double* buf = nullptr;
+    size_t nd = 0;
+    const size_t o_phi = nd; if (phi && (mask & LBM_PHI)) nd += N;
+    const size_t o_P = nd; if (P && (mask & LBM_P)) nd += N;
+    const size_t o_u = nd; if (u && (mask & LBM_U)) nd += 3 * N;
+    const size_t o_pop = nd; if (want_pop) nd += (size_t)(QH + QG) * N;
+    if (nd) HIPCHK(hipMalloc(&buf, nd * sizeof(double)));
+    ReadOut ro;
+    ro.phi = (phi && (mask & LBM_PHI)) ? buf + o_phi : nullptr;
+    ro.P = (P && (mask & LBM_P)) ? buf + o_P : nullptr;
+    ro.u = (u && (mask & LBM_U)) ? buf + o_u : nullptr;
+    ro.pops = want_pop ? buf + o_pop : nullptr;
+    InitIn in = {nullptr, nullptr};
+    hipError_t e = launch_phi(storage, parity, d_desc, d_tiles, ntiles, s, 1);
+    if (e == hipSuccess) e = launch_sweep(storage, MODE_READ, hdesc.tx, parity, d_desc, d_tiles, ntiles, 1, ro, in, s);
+    if (e == hipSuccess && ro.phi) e = hipMemcpyAsync(phi, ro.phi, N * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && ro.P) e = hipMemcpyAsync(P, ro.P, N * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && ro.u) e = hipMemcpyAsync(u, ro.u, 3 * N * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && ro.pops) {
+        double* dst = pops;
+        if (mask & LBM_POP_H) {
+            e = hipMemcpyAsync(dst, ro.pops, (size_t)QH * N * sizeof(double), hipMemcpyDeviceToHost, s);
+            dst += (size_t)QH * N;
+        }
+        if (e == hipSuccess && (mask & LBM_POP_G))
+            e = hipMemcpyAsync(dst, ro.pops + (size_t)QH * N, (size_t)QG * N * sizeof(double),
+                               hipMemcpyDeviceToHost, s);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (buf) hipFree(buf);
+    if (e != hipSuccess) { set_error("read fields: %s", hipGetErrorString(e)); return LBM_E_DEVICE; }
+    return LBM_OK;
+}
+
+}  // namespace pflbm

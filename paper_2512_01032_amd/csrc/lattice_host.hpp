@@ -1,0 +1,63 @@
+// lattice_host.hpp -- host-side construction of one lattice's device state:
+// parameter validation, node classification, tile table, arena layout and the
+// descriptor.  Shared by the single-lattice API and the serving scheduler.
+#pragma once
+
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "pflbm.hpp"
+
+namespace pflbm {
+
+void set_error(const char* fmt, ...);
+
+struct LatticeLayout {
+    int tx = 64, ty = 4, tz = 16;
+    int64_t N = 0;
+    int64_t n_fluid = 0, n_ghost = 0, n_solid = 0;
+    size_t off_desc = 0, off_counter = 0, off_h = 0, off_g = 0, off_phi = 0, off_flag = 0,
+           off_link = 0, off_tiles = 0, off_partials = 0, total = 0;
+    std::vector<uint8_t> flag;
+    std::vector<uint32_t> link;
+    std::vector<Tile> tiles;
+};
+
+// Validate parameters (and geometry when given).  Returns LBM_OK or sets the
+// error message and returns LBM_E_INVAL.
+int validate_params(const lbm_params* p, const lbm_geometry* geo);
+
+// Tile width for a lattice of width nx; tile depth for a given tile count target.
+int choose_tx(int nx);
+int choose_tz(const lbm_params* p, int tx);
+
+// Bytes per stored population of each lattice.
+void storage_sizes(int storage, int* sh, int* sg, int* sphi);
+
+// Sizes only (no geometry): used by lbm_footprint; assumes every tile is kept.
+size_t footprint_bytes(const lbm_params* p);
+
+// Full classification + tile table + offsets.  lat: lattice index stamped in
+// the tiles.  Returns LBM_OK or LBM_E_INVAL.
+int build_layout(const lbm_params* p, const lbm_geometry* geo, int lat, LatticeLayout* L);
+
+// Descriptor for device pointers rooted at base (device address of the arena).
+void fill_desc(const lbm_params* p, const lbm_geometry* geo, const LatticeLayout& L,
+               char* base, int64_t step, Desc* d);
+
+// Upload flags, links, tiles and descriptor to a device arena at base, then
+// initialise the populations (FIELDS or POPULATIONS).  Synchronous on s.
+int upload_and_init(const lbm_params* p, const lbm_geometry* geo, const lbm_init* init,
+                    LatticeLayout& L, char* base, Desc* hdesc, hipStream_t s);
+
+// Read fields of one lattice whose descriptor is at d_desc and tiles at
+// d_tiles (device).  Synchronous.
+// parity: AA parity of the lattice's current step.
+int read_lattice(int storage, const Desc& hdesc, int parity, Desc* d_desc, const Tile* d_tiles,
+                 int ntiles, uint32_t mask, double* phi, double* P, double* u, double* pops,
+                 hipStream_t s);
+
+}  // namespace pflbm

@@ -1,0 +1,123 @@
+// pflbm.hpp -- device-side data layout of the MI355X phase-field LB library.
+//
+// One lattice lives in HBM as
+//   h   [7][N]  phase-field populations (D3Q7), structure of arrays, x fastest
+//   g   [19][N] hydrodynamic populations (D3Q19)
+//   phi [N]     order parameter of the current step (written by the phi pass)
+//   flag[N]     node kind / material / face / near-wall / ghost-owner bits
+//   link[N]     per-node solid-link mask and owned pressure faces
+// and is swept in tiles of TX x TY = 256 columns marching over a z-chunk.
+// Several lattices (serving) share one tile table; every tile names its
+// lattice, and each lattice's descriptor carries its own parameters, step
+// counter and parity.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pflbm {
+
+constexpr int QH = 7;
+constexpr int QG = 19;
+constexpr int NTHREADS = 256;       // threads per tile / workgroup
+constexpr int NPART = 10;           // FP64 diagnostic partials per tile
+
+// flag byte
+constexpr uint8_t KIND_FLUID = 0, KIND_SOLID = 1, KIND_GHOST = 2;
+constexpr uint8_t F_KIND_MASK = 0x3;
+constexpr uint8_t F_NEAR_WALL = 0x40;  // fluid node with at least one solid link
+constexpr uint8_t F_OWNER = 0x80;      // fluid node that feeds a pressure ghost
+__host__ __device__ inline int flag_kind(uint8_t f) { return f & F_KIND_MASK; }
+__host__ __device__ inline int flag_sub(uint8_t f) { return (f >> 2) & 15; }  // material or face
+__host__ __device__ inline uint8_t make_flag(int kind, int sub) {
+    return (uint8_t)(kind | (sub << 2));
+}
+// link word: bit i (1..18) = neighbour x + c_i is solid; bit 24+f = this node
+// is the owner (inward neighbour) of a ghost on pressure face f
+constexpr int LINK_OWNER_SHIFT = 24;
+
+// storage modes (same values as enum lbm_storage)
+constexpr int ST_FP64 = 0, ST_FP32 = 1, ST_FP32_SHIFT = 2, ST_FP16_G = 3, ST_FP16_ALL = 4;
+
+struct alignas(16) Tile {
+    int32_t lat;      // lattice index in the descriptor array
+    int32_t x0, y0;   // first column of the tile
+    int32_t z0, zn;   // z-chunk [z0, z0 + zn)
+    int32_t tile_in_lat;  // index of this tile within its lattice (partials slot)
+    int32_t pad[2];
+};
+
+// per-lattice descriptor, resident in device memory
+struct alignas(256) Desc {
+    // layout
+    int32_t nx, ny, nz, tx;        // tx: tile width (16, 32 or 64); ty = 256 / tx
+    int64_t N;
+    int32_t storage;
+    int32_t ntiles;                // tiles of this lattice
+    void* h;
+    void* g;
+    void* hq[7];                   // h + q N: base of each direction
+    void* gq[19];
+    void* phi;
+    const uint8_t* flag;
+    const uint32_t* link;
+    double* partials;              // [ntiles][NPART]
+    unsigned int* counter;         // tiles finished in the current sweep
+    // time
+    int64_t step;                  // advanced on the device by the last tile of a sweep
+    int64_t t0;                    // step counter value at physical time 0
+    int64_t stop_step;             // the sweep leaves the lattice alone from here on
+    int64_t diag_every;            // 0: never
+    // physics
+    double rho_l, rho_g, nu_l, nu_g, sigma, W, M;
+    double F[3];
+    int32_t mobility_corr, mix, friction, pad0;
+    double mc_gamma, mc_phi_M, mc_phi_m, mc_D, eps;
+    double mix_phi, mix_width;
+    double slip_lo, slip_hi;
+    double P_ref;
+    int32_t face_bc[6];
+    double face_P[6], face_ramp[6];
+    double cos_t[16], sin_t[16];
+    double clamp_a;
+    double href, gref;             // shift references (0 for plain storage)
+    double scale_h, scale_g;       // storage scales (1 except FP16)
+    double u_max;
+    // outputs of the last diagnostic reduction
+    double diag[NPART];
+    int64_t diag_step;
+    int32_t unstable;              // sticky: NaN or |u| > u_max seen
+    int32_t pad1;
+};
+
+// diagnostic partial slots
+enum { P_PHI = 0, P_MX, P_MY, P_MZ, P_UMAX, P_NAN, P_PLIQ, P_NLIQ, P_PGAS, P_NGAS };
+
+// kernel modes of the sweep
+constexpr int MODE_STEP = 0;   // stream + collide, AA in place
+constexpr int MODE_READ = 1;   // macroscopic fields / populations to output buffers
+constexpr int MODE_INIT = 2;   // equilibria from (phi, u, P) into even-parity slots
+
+struct ReadOut {               // device buffers of MODE_READ (NULL: skip)
+    double* phi;
+    double* P;
+    double* u;                 // [3][N]
+    double* pops;              // [26][N]: h then g
+};
+
+struct InitIn {                // device inputs of MODE_INIT
+    const double* u;           // [3][N] or NULL
+    const double* P;           // [N] or NULL
+};
+
+// host-side launchers (kernels.hip).  parity: AA parity of the step every
+// lattice in the table is at; tx: tile width of every tile (16, 32 or 64).
+// force: run the phi pass even for lattices past their stop step (read-back).
+hipError_t launch_phi(int storage, int parity, const Desc* d, const Tile* tiles, int ntiles,
+                      hipStream_t s, int force = 0);
+hipError_t launch_sweep(int storage, int mode, int tx, int parity, Desc* d, const Tile* tiles,
+                        int ntiles, int diag, ReadOut ro, InitIn in, hipStream_t s);
+hipError_t launch_restore(int storage, int parity, const Desc* d, const Tile* tiles, int ntiles,
+                          const double* pops, hipStream_t s);
+
+}  // namespace pflbm

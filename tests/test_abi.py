@@ -1,0 +1,125 @@
+"""The C-ABI library loads and exports every entry point include/lbm.h
+declares; host-side validation works without a GPU (no compute calls)."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("lbm_create", "lbm_step", "lbm_read_fields", "lbm_submit", "lbm_footprint",
+                 "lbm_reduce", "lbm_destroy", "lbm_poll"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2512_01032_amd import lbm
+    L = ctypes.CDLL(lbm.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+    assert set(lbm.EXPORTED) == set(declared_functions())
+
+
+def test_struct_sizes_match_header():
+    """Compile a tiny C program against include/lbm.h and compare the sizes
+    and field offsets the ctypes mirror uses."""
+    import subprocess
+    import tempfile
+    from paper_2512_01032_amd import lbm
+    src = r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "lbm.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(lbm_params), sizeof(lbm_geometry),
+         sizeof(lbm_init), sizeof(lbm_device_ctx), sizeof(lbm_diag), sizeof(lbm_info),
+         sizeof(lbm_server_cfg), sizeof(lbm_request), sizeof(lbm_result));
+  printf("%zu %zu %zu\n", offsetof(lbm_params, face_bc), offsetof(lbm_params, diag_every),
+         offsetof(lbm_params, fp16_log2_scale_g));
+  return 0;
+}
+'''
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "s.c")
+        exe = os.path.join(d, "s")
+        open(c, "w").write(src)
+        subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
+        out = subprocess.check_output([exe]).decode().split("\n")
+    sizes = [int(v) for v in out[0].split()]
+    mine = [ctypes.sizeof(t) for t in (lbm.lbm_params, lbm.lbm_geometry, lbm.lbm_init,
+                                       lbm.lbm_device_ctx, lbm.lbm_diag, lbm.lbm_info,
+                                       lbm.lbm_server_cfg, lbm.lbm_request, lbm.lbm_result)]
+    assert sizes == mine
+    offs = [int(v) for v in out[1].split()]
+    assert offs == [lbm.lbm_params.face_bc.offset, lbm.lbm_params.diag_every.offset,
+                    lbm.lbm_params.fp16_log2_scale_g.offset]
+
+
+@pytest.mark.parametrize("field,value", [("nu_l", 0.0), ("W", -1.0), ("rho_g", 0.0), ("nx", 0),
+                                         ("storage", 9)])
+def test_invalid_parameters_rejected_on_host(field, value):
+    from paper_2512_01032_amd import inputs, lbm
+    wl = inputs.random_small(8, 6, 5, seed=0)
+    p = lbm.params_from_workload(wl)
+    setattr(p, field, value)
+    assert lbm.lbm_footprint(ctypes.byref(p)) == 0
+    with pytest.raises(lbm.LbmError) as ei:
+        wl2 = wl
+        g = lbm.lbm_geometry()
+        for k in range(16):
+            g.theta_deg[k] = 90.0
+        init = lbm.lbm_init()
+        phi = wl2.phi0.copy()
+        init.phi = phi.ctypes.data
+        h = ctypes.c_void_p()
+        lbm.check(lbm.lbm_create(ctypes.byref(p), ctypes.byref(g), ctypes.byref(init), None,
+                                 ctypes.byref(h)))
+    assert ei.value.code == lbm.LBM_E_INVAL
+
+
+def test_invalid_geometry_rejected_on_host():
+    from paper_2512_01032_amd import inputs, lbm
+    import numpy as np
+    wl = inputs.random_small(8, 6, 5, seed=0)
+    wl.theta_deg = (0.0,) + (90.0,) * 15                 # angle outside (0, 180)
+    with pytest.raises(lbm.LbmError) as ei:
+        lbm.Lattice(wl)
+    assert ei.value.code == lbm.LBM_E_INVAL
+    wl = inputs.random_small(8, 6, 5, seed=0, open_x=True)
+    wl.faces = (wl.faces[0], wl.faces[1], (0.3, 0.0), None, None, None)   # two pressure faces meet
+    with pytest.raises(lbm.LbmError) as ei:
+        lbm.Lattice(wl)
+    assert ei.value.code == lbm.LBM_E_INVAL
+    wl = inputs.random_small(8, 6, 5, seed=0, open_x=True)
+    s = np.zeros(wl.shape, np.uint8)
+    s[:, :, 1] = 1                                      # ghost at x = 0 with a solid owner
+    wl.solid = s
+    with pytest.raises(lbm.LbmError) as ei:
+        lbm.Lattice(wl)
+    assert ei.value.code == lbm.LBM_E_INVAL
+
+
+def test_footprint_counts_populations():
+    from paper_2512_01032_amd import inputs, lbm
+    wl = inputs.random_small(64, 16, 16, seed=0)
+    n = 64 * 16 * 16
+    f32 = lbm.footprint(wl, "fp32_shift")
+    f16 = lbm.footprint(wl, "fp16_shift_g")
+    f64 = lbm.footprint(wl, "fp64")
+    assert f32 >= n * (26 * 4 + 4 + 1 + 4)
+    assert f64 >= n * (26 * 8 + 8 + 1 + 4)
+    assert f16 >= n * (7 * 4 + 19 * 2 + 4 + 1 + 4)
+    assert f16 < f32 < f64

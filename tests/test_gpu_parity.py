@@ -1,0 +1,198 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerances (max |gpu - oracle| / max |oracle| per field over fluid nodes):
+* FP64 storage: 1e-10 after up to 200 steps for phi, P and the populations h
+  and g; phi-mass drift <= 1e-12 relative.  The velocity is a sum of +-g_i
+  terms of size P/T ~ 1 divided by rho:
+    - u divides by rho_g = 1e-3 in the gas, so it is compared as momentum
+      rho u (both sides use the oracle's rho);
+    - momentum is held to 1e-10 relative to its own maximum when the flow
+      carries it (a translating droplet), and to 1e-10 relative to the size
+      of the summed terms, max sum_i |g_i|, in the near-static droplet whose
+      momentum is 1e-5 of those terms (its rounding lives on that scale).
+* FP32 shifted storage: 1e-5 for phi and the populations, 1e-3 for P and
+  rho u after 200 steps.  FP32 rounding is 6e-8 per operation and the
+  collision feeds its rounding back through the moments every step.
+* Plain FP32 storage keeps phi and the populations to 1e-5 but rounds g ~ w_i
+  to 3e-8 absolute, which is 1e-5 in u in the gas: its velocity error is
+  reported, not bounded (the reason the shifted storage exists).
+* FP16 storage of g (h in FP32): phi within 1e-3 after 50 steps on walls and
+  pressure faces.  FP16 storage of h as well: reported only (see DESIGN).
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+from tests.gpu_util import compare_state, rel_err, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _lbm():
+    require_gpu()
+    from paper_2512_01032_amd import lbm
+    return lbm
+
+
+def _run_pair(wl, steps, storage="fp64"):
+    from oracle import ref
+    lbm = _lbm()
+    print("case %s storage=%s steps=%d shape=%s" % (wl.name, storage, steps, wl.shape), flush=True)
+    g = lbm.Lattice(wl, storage=storage)
+    o = ref.Oracle(wl)
+    g.step(steps)
+    g.sync()
+    o.step(steps)
+    return g, o
+
+
+FP64_TOL = 1e-10
+
+
+STRICT = ("phi", "P", "h", "g", "mom")
+
+
+def test_c1_static_droplet_fp64_200_steps():
+    from paper_2512_01032_amd import inputs
+    wl = inputs.static_droplet()
+    g, o = _run_pair(wl, 200)
+    err = compare_state(g, o, o.kinds())
+    print(err, flush=True)
+    for k in ("phi", "P", "h", "g", "mom_sum"):
+        assert err[k] <= FP64_TOL, (k, err[k])
+    d0 = float(np.sum(wl.phi0))
+    dg = g.diagnostics()
+    do = o.diagnostics()
+    assert abs(dg["phi_sum"] - do["phi_sum"]) <= 1e-12 * abs(do["phi_sum"])
+    # mass drift of the GPU run against the initial field
+    assert abs(dg["phi_sum"] - d0) <= 1e-12 * d0
+    assert dg["n_nan"] == 0
+    # |u| carries the gas-phase 1/rho_g amplification (module docstring)
+    assert abs(dg["u_max"] - do["u_max"]) <= 1e-6 * do["u_max"]
+
+
+@pytest.mark.parametrize("shape,kw,steps", [
+    ((8, 6, 7), dict(), 7),
+    ((8, 6, 7), dict(walls=True), 7),
+    ((8, 6, 7), dict(walls=True, open_x=True), 9),
+    ((8, 6, 7), dict(walls=True, open_x=True, optimised_model=True), 9),
+    ((70, 13, 9), dict(walls=True, open_x=True), 11),      # several tiles, ragged x and y
+    ((33, 40, 5), dict(walls=True), 6),                     # TX = 16 tiles, ragged
+    ((130, 5, 3), dict(open_x=True, optimised_model=True), 5),  # TX = 64, ragged
+])
+def test_small_lattices_fp64(shape, kw, steps):
+    from paper_2512_01032_amd import inputs
+    wl = inputs.random_small(*shape, seed=11, **kw)
+    g, o = _run_pair(wl, steps)
+    err = compare_state(g, o, o.kinds())
+    print(err, flush=True)
+    for k in STRICT:
+        assert err[k] <= FP64_TOL, (k, err[k])
+
+
+def test_quasi_2d_and_tiny_fp64():
+    from paper_2512_01032_amd import inputs
+    for shape in [(40, 1, 12), (4, 4, 4), (1, 1, 9)]:
+        wl = inputs.random_small(*shape, seed=5, walls=shape[1] > 1)
+        g, o = _run_pair(wl, 5)
+        err = compare_state(g, o, o.kinds())
+        print(shape, err, flush=True)
+        for k in STRICT:
+            assert err[k] <= FP64_TOL, (shape, k, err[k])
+
+
+def test_restore_and_determinism_fp64():
+    """20 steps in one go == 10 steps, read populations, restore, 10 steps
+    (bitwise), and two identical runs agree bitwise."""
+    from paper_2512_01032_amd import inputs
+    lbm = _lbm()
+    wl = inputs.random_small(24, 10, 12, seed=3, walls=True, open_x=True)
+    a = lbm.Lattice(wl, storage="fp64")
+    a.step(20)
+    ha, ga = a.pops()
+    b = lbm.Lattice(wl, storage="fp64")
+    b.step(20)
+    hb, gb = b.pops()
+    assert np.array_equal(ha, hb) and np.array_equal(ga, gb)
+    c = lbm.Lattice(wl, storage="fp64")
+    c.step(11)   # odd step: restore into the odd-parity layout
+    hc, gc = c.pops()
+    d = lbm.Lattice(wl, storage="fp64", pops=np.concatenate([hc, gc]), step=11)
+    d.step(9)
+    hd, gd = d.pops()
+    assert np.array_equal(hd, ha) and np.array_equal(gd, ga)
+
+
+def test_translating_droplet_fp64():
+    """A droplet carried by a uniform flow: momentum is O(1e-2) and is held to
+    1e-10 relative to its maximum."""
+    from paper_2512_01032_amd import inputs
+    wl = inputs.static_droplet(n=32, R=7.0, steps=120)
+    wl.u0 = np.zeros((3,) + wl.shape)
+    wl.u0[0] = 0.02
+    wl.u0[1] = -0.01
+    g, o = _run_pair(wl, 120)
+    err = compare_state(g, o, o.kinds())
+    print(err, flush=True)
+    for k in STRICT + ("u_raw",):
+        assert err[k] <= FP64_TOL, (k, err[k])
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp32_shift"])
+def test_c1_fp32_modes(storage):
+    from paper_2512_01032_amd import inputs
+    wl = inputs.static_droplet()
+    g, o = _run_pair(wl, 200, storage)
+    err = compare_state(g, o, o.kinds())
+    print(storage, err, flush=True)
+    assert err["phi"] <= 1e-5 and err["h"] <= 1e-5 and err["g"] <= 2e-5, err
+    if storage == "fp32_shift":
+        assert err["P"] <= 1e-3 and err["mom"] <= 1e-3, err
+
+
+@pytest.mark.parametrize("storage", ["fp32_shift", "fp16_shift_g", "fp16_shift_all"])
+def test_walls_open_faces_reduced_precision(storage):
+    """Reduced-precision storage on walls + pressure faces (module docstring)."""
+    from paper_2512_01032_amd import inputs
+    wl = inputs.random_small(40, 12, 10, seed=8, walls=True, open_x=True, optimised_model=True,
+                             u_amp=0.002)
+    g, o = _run_pair(wl, 50, storage)
+    err = compare_state(g, o, o.kinds())
+    print(storage, err, flush=True)
+    assert all(np.isfinite(v) for v in err.values()), err
+    if storage == "fp16_shift_all":
+        return   # reported only
+    bound = {"fp32_shift": 1e-5, "fp16_shift_g": 1e-3}[storage]
+    assert err["phi"] <= bound, err
+
+
+def test_diagnostics_match_oracle():
+    from paper_2512_01032_amd import inputs
+    wl = inputs.random_small(30, 14, 11, seed=2, walls=True, open_x=True)
+    g, o = _run_pair(wl, 13)
+    dg, do = g.diagnostics(), o.diagnostics()
+    print(dg, do, flush=True)
+    for k in ("phi_sum", "P_liq_mean", "P_gas_mean"):
+        assert abs(dg[k] - do[k]) <= 1e-10 * max(abs(do[k]), 1e-30), k
+    assert abs(dg["u_max"] - do["u_max"]) <= 1e-6 * do["u_max"]
+    for a in range(3):
+        assert abs(dg["mom"][a] - do["mom"][a]) <= 1e-10 * max(map(abs, do["mom"])) + 1e-300
+    for k in ("n_nan", "n_liq", "n_gas"):
+        assert dg[k] == do[k], k
+
+
+def test_unstable_flag_from_seeded_nan():
+    """A NaN planted in phi0 (host-side input) is caught by the next
+    diagnostic step and reported as LBM_E_UNSTABLE."""
+    from paper_2512_01032_amd import inputs
+    lbm = _lbm()
+    wl = inputs.random_small(16, 8, 8, seed=1)
+    wl.phi0[3, 3, 3] = np.nan
+    g = lbm.Lattice(wl, storage="fp32_shift", diag_every=1, u_max=0.5)
+    g.step(2)
+    with pytest.raises(lbm.LbmError) as ei:
+        g.sync()
+    assert ei.value.code == lbm.LBM_E_UNSTABLE
