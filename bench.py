@@ -1,0 +1,204 @@
+"""Throughput of the fused phase-field LB step on one MI355X.
+
+Workload: the constricted duct, 256 x 256 x 512 nodes (square duct along z,
+step constriction to half width at z = 256, contact angle 120 deg, density
+ratio 1000, viscosity ratio 100, seeded liquid slugs, inlet pressure ramp),
+synthetic inputs from paper_2512_01032_amd.inputs.constricted_duct().
+
+One step = the phi pass + the fused stream-collide sweep over every node.
+`value` is million fluid-node updates per second (MLUPS) with the lattice
+resident in HBM, FP32 shifted-population storage; FP16-stored populations
+(g in FP16, h in FP32) and the plain FP64 / FP32 storage are reported beside
+it, each with max |phi - oracle| after a short run.  The roofline object is
+for the sweep kernel (the dominant one): algorithmic bytes = 2 (7 s_h +
+19 s_g) per fluid node (every population read once and written once) over
+the sweep's average duration measured with HIP events on its stream.  The
+CPU baseline is the FP64 oracle on the host cores, on a bounded sample: the
+same lattice for a few steps.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "MLUPS + % HBM roofline, FP32 vs FP16-store at stated error; p99 solve latency"
+SOURCES = ["paper_2512_01032_amd/csrc/kernels_impl.hpp", "paper_2512_01032_amd/csrc/pflbm.hpp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_traffic_constricted_duct.json")
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for s in SOURCES:
+        h.update(open(os.path.join(ROOT, s), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(storage):
+    """HBM bytes per sweep launch from the committed rocprofv3 counter runs,
+    if they were taken on the current kernel source."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_hash") != kernel_hash():
+        return None
+    return rec.get("bytes_per_sweep", {}).get(storage)
+
+
+def run_gpu(wl, storage, steps, warmup, torch):
+    from paper_2512_01032_amd import lbm
+    stream = torch.cuda.current_stream()
+    lat = lbm.Lattice(wl, storage=storage, stream=stream.cuda_stream)
+    info = lat.info()
+    lat.step(warmup)
+    lat.sync()
+    lat.get_timing()
+    lat.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.step(steps)
+    lat.sync()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    phi_ms, sweep_ms, n = lat.get_timing()
+    lat.set_timing(False)
+    return lat, info, el, phi_ms / max(n, 1), sweep_ms / max(n, 1)
+
+
+def storage_bytes(storage):
+    return {"fp64": (8, 8), "fp32": (4, 4), "fp32_shift": (4, 4),
+            "fp16_shift_g": (4, 2), "fp16_shift_all": (2, 2)}[storage]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--modes", default="fp32_shift,fp16_shift_g,fp32,fp64")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the lattice of this workload fits one MI355X and "
+              "the multi-GPU (z-slab halo exchange) path is not built; use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2512_01032_amd import inputs
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+
+    wl = inputs.constricted_duct()
+    modes = args.modes.split(",")
+    results = {}
+    lattices = {}
+    for m in modes:
+        print("[bench] %s: %d warmup + %d timed steps" % (m, args.warmup, args.steps),
+              file=sys.stderr, flush=True)
+        lat, info, el, phi_ms, sweep_ms = run_gpu(wl, m, args.steps, args.warmup, torch)
+        sh, sg = storage_bytes(m)
+        b_alg = 2 * (7 * sh + 19 * sg)
+        nf, nn = info["n_fluid"], info["n_nodes"]
+        achieved = b_alg * nf / (sweep_ms * 1e-3) / 1e9
+        results[m] = {
+            "mlups_fluid": nf * args.steps / el / 1e6,
+            "mlups_total_nodes": nn * args.steps / el / 1e6,
+            "ms_per_step": el / args.steps * 1e3,
+            "phi_pass_ms": phi_ms,
+            "sweep_ms": sweep_ms,
+            "bytes_per_fluid_update": b_alg,
+            "sweep_GBs": achieved,
+            "sweep_frac_hbm": achieved / HBM_PEAK_GBS,
+            "step_GBs_alg": b_alg * nf * args.steps / el / 1e9,
+        }
+        lattices[m] = lat
+        print("[bench] %s: %.1f MLUPS (fluid), sweep %.3f ms, phi %.3f ms, %.0f GB/s alg"
+              % (m, results[m]["mlups_fluid"], sweep_ms, phi_ms, achieved),
+              file=sys.stderr, flush=True)
+        if m not in ("fp32_shift", "fp16_shift_g"):
+            lat.close()
+            del lattices[m]
+
+    primary = results["fp32_shift"]
+    info_nf = None
+    cpu = None
+    errors = {}
+    if not args.no_cpu_baseline:
+        # FP64 oracle on the host cores, bounded sample: this lattice, a few
+        # steps; the same steps on the GPU give max |phi - oracle|
+        from oracle import ref
+        cores = len(os.sched_getaffinity(0))
+        print("[bench] cpu baseline: oracle on %d cores, %d steps" % (cores, args.cpu_steps),
+              file=sys.stderr, flush=True)
+        o = ref.Oracle(wl)
+        t0 = time.perf_counter()
+        o.step(args.cpu_steps)
+        el = time.perf_counter() - t0
+        kinds = o.kinds()
+        nf = int((kinds == 0).sum())
+        cpu = {"value": nf * args.cpu_steps / el / 1e6, "unit": "MLUPS", "cores": cores,
+               "kind": "oracle",
+               "sample": "full 256x256x512 lattice, %d steps after initialisation, "
+                         "FP64, OpenMP over %d host threads" % (args.cpu_steps, cores)}
+        phi_o = o.fields()[0]
+        fluid = kinds == 0
+        from paper_2512_01032_amd import lbm
+        for m in ("fp32_shift", "fp16_shift_g"):
+            g = lbm.Lattice(wl, storage=m)
+            g.step(args.cpu_steps)
+            phi_g = g.fields()[0]
+            errors[m] = float(np.abs(phi_g - phi_o)[fluid].max())
+            g.close()
+        del o
+
+    sh, sg = storage_bytes("fp32_shift")
+    b_alg = 2 * (7 * sh + 19 * sg)
+    traffic = measured_traffic("fp32_shift")
+    line = {
+        "metric": METRIC,
+        "value": round(primary["mlups_fluid"], 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(primary["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "constricted_duct_256x256x512", "storage": "fp32_shift",
+                   "nodes": wl.n_nodes, "value_counts": "fluid-node updates",
+                   "density_ratio": 1000, "contact_angle_deg": 120},
+        "roofline": {"bound": "hbm", "achieved": round(primary["sweep_GBs"], 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(primary["sweep_frac_hbm"], 4),
+                     "traffic": traffic,
+                     "kernel": "sweep_kernel (fused stream-collide)",
+                     "bytes_per_unit": b_alg, "unit_count": "fluid nodes per launch"},
+        "cpu_baseline": cpu,
+        "modes": {m: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
+                  for m, r in results.items()},
+        "max_abs_dphi_vs_oracle": errors,
+        "kernel_hash": kernel_hash(),
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

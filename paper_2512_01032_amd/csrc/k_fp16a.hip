@@ -19,4 +19,8 @@ hipError_t launch_restore_fp16a(int parity, const Desc* d, const Tile* tiles, in
     return launch_restore_storage<float, _Float16, _Float16>(parity, d, tiles, ntiles, pops, s);
 }
 
+hipError_t launch_ghosts_fp16a(const Desc* d, const GhostRef* ghosts, int nghosts, hipStream_t s) {
+    return launch_ghosts_storage<float, _Float16, _Float16>(d, ghosts, nghosts, s);
+}
+
 }  // namespace pflbm

@@ -19,4 +19,8 @@ hipError_t launch_restore_fp32(int parity, const Desc* d, const Tile* tiles, int
     return launch_restore_storage<float, float, float>(parity, d, tiles, ntiles, pops, s);
 }
 
+hipError_t launch_ghosts_fp32(const Desc* d, const GhostRef* ghosts, int nghosts, hipStream_t s) {
+    return launch_ghosts_storage<float, float, float>(d, ghosts, nghosts, s);
+}
+
 }  // namespace pflbm

@@ -19,4 +19,8 @@ hipError_t launch_restore_fp64(int parity, const Desc* d, const Tile* tiles, int
     return launch_restore_storage<double, double, double>(parity, d, tiles, ntiles, pops, s);
 }
 
+hipError_t launch_ghosts_fp64(const Desc* d, const GhostRef* ghosts, int nghosts, hipStream_t s) {
+    return launch_ghosts_storage<double, double, double>(d, ghosts, nghosts, s);
+}
+
 }  // namespace pflbm

@@ -8,15 +8,19 @@ namespace pflbm {
 hipError_t launch_sweep_fp64(int, int, int, Desc*, const Tile*, int, int, ReadOut, InitIn, hipStream_t);
 hipError_t launch_phi_fp64(int, const Desc*, const Tile*, int, hipStream_t, int);
 hipError_t launch_restore_fp64(int, const Desc*, const Tile*, int, const double*, hipStream_t);
+hipError_t launch_ghosts_fp64(const Desc*, const GhostRef*, int, hipStream_t);
 hipError_t launch_sweep_fp32(int, int, int, Desc*, const Tile*, int, int, ReadOut, InitIn, hipStream_t);
 hipError_t launch_phi_fp32(int, const Desc*, const Tile*, int, hipStream_t, int);
 hipError_t launch_restore_fp32(int, const Desc*, const Tile*, int, const double*, hipStream_t);
+hipError_t launch_ghosts_fp32(const Desc*, const GhostRef*, int, hipStream_t);
 hipError_t launch_sweep_fp16g(int, int, int, Desc*, const Tile*, int, int, ReadOut, InitIn, hipStream_t);
 hipError_t launch_phi_fp16g(int, const Desc*, const Tile*, int, hipStream_t, int);
 hipError_t launch_restore_fp16g(int, const Desc*, const Tile*, int, const double*, hipStream_t);
+hipError_t launch_ghosts_fp16g(const Desc*, const GhostRef*, int, hipStream_t);
 hipError_t launch_sweep_fp16a(int, int, int, Desc*, const Tile*, int, int, ReadOut, InitIn, hipStream_t);
 hipError_t launch_phi_fp16a(int, const Desc*, const Tile*, int, hipStream_t, int);
 hipError_t launch_restore_fp16a(int, const Desc*, const Tile*, int, const double*, hipStream_t);
+hipError_t launch_ghosts_fp16a(const Desc*, const GhostRef*, int, hipStream_t);
 
 hipError_t launch_sweep(int storage, int mode, int tx, int parity, Desc* d, const Tile* tiles,
                         int ntiles, int diag, ReadOut ro, InitIn in, hipStream_t s) {
@@ -50,6 +54,18 @@ hipError_t launch_restore(int storage, int parity, const Desc* d, const Tile* ti
         case ST_FP32_SHIFT: return launch_restore_fp32(parity, d, tiles, ntiles, pops, s);
         case ST_FP16_G: return launch_restore_fp16g(parity, d, tiles, ntiles, pops, s);
         case ST_FP16_ALL: return launch_restore_fp16a(parity, d, tiles, ntiles, pops, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_ghosts(int storage, const Desc* d, const GhostRef* ghosts, int nghosts,
+                         hipStream_t s) {
+    switch (storage) {
+        case ST_FP64: return launch_ghosts_fp64(d, ghosts, nghosts, s);
+        case ST_FP32:
+        case ST_FP32_SHIFT: return launch_ghosts_fp32(d, ghosts, nghosts, s);
+        case ST_FP16_G: return launch_ghosts_fp16g(d, ghosts, nghosts, s);
+        case ST_FP16_ALL: return launch_ghosts_fp16a(d, ghosts, nghosts, s);
     }
     return hipErrorInvalidValue;
 }

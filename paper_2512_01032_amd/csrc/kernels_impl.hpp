@@ -139,44 +139,23 @@ template <typename S, int Q> __device__ inline PopArray<S, Q> pop_array(void* ba
 }
 
 // ----------------------------------------------------------- parameters
+// Derived constants come precomputed in the compute precision (Desc::pf for
+// FP32, Desc::pd for FP64) and are read through a uniform pointer, so they
+// live in scalar registers.
+template <typename T> __device__ inline const T* param_block(const Desc* D);
+template <> __device__ inline const float* param_block<float>(const Desc* D) { return D->pf; }
+template <> __device__ inline const double* param_block<double>(const Desc* D) { return D->pd; }
+
 template <typename T> struct Phys {
-    T rho_g, rdif, sigma, W, M, F[3];
-    T tau_l, tau_g;
-    T mc_gamma, mc_phi_M, mc_phi_m, mc_invD, eps;
-    T mix_phi, mix_invw;
-    T slip_lo, slip_hi;
-    T clamp_a;
-    T href, gref, sh, sg, inv_sh, inv_sg;
+    const T* __restrict__ p;
     int mobility_corr, mix, friction;
     __device__ void load(const Desc* D) {
-        rho_g = uni((T)D->rho_g);
-        rdif = uni((T)(D->rho_l - D->rho_g));
-        sigma = uni((T)D->sigma);
-        W = uni((T)D->W);
-        M = uni((T)D->M);
-        F[0] = uni((T)D->F[0]); F[1] = uni((T)D->F[1]); F[2] = uni((T)D->F[2]);
-        tau_l = uni((T)(D->nu_l / TGc + 0.5));
-        tau_g = uni((T)(D->nu_g / TGc + 0.5));
-        mc_gamma = uni((T)D->mc_gamma);
-        mc_phi_M = uni((T)D->mc_phi_M);
-        mc_phi_m = uni((T)D->mc_phi_m);
-        mc_invD = uni((T)(1.0 / D->mc_D));
-        eps = uni((T)D->eps);
-        mix_phi = uni((T)D->mix_phi);
-        mix_invw = uni((T)(1.0 / D->mix_width));
-        slip_lo = uni((T)D->slip_lo);
-        slip_hi = uni((T)D->slip_hi);
-        clamp_a = uni((T)D->clamp_a);
-        href = uni((T)D->href);
-        gref = uni((T)D->gref);
-        sh = uni((T)D->scale_h);
-        sg = uni((T)D->scale_g);
-        inv_sh = uni((T)(1.0 / D->scale_h));
-        inv_sg = uni((T)(1.0 / D->scale_g));
+        p = unip(param_block<T>(D));
         mobility_corr = uni(D->mobility_corr);
         mix = uni(D->mix);
         friction = uni(D->friction);
     }
+    __device__ T operator[](int k) const { return p[k]; }
 };
 
 template <typename T> __device__ inline T clamp01(T v) { return v < T(0) ? T(0) : (v > T(1) ? T(1) : v); }
@@ -275,11 +254,11 @@ __device__ inline T phase_sum(const PopArray<SH, QH>& h, const uint8_t* flg, con
     Nbr nb;
     nb.init(x, y, z, nx, ny, nz);
     T d[QH];
-    read_pops<T, SH, QH, PAR>(h, (uint32_t)n, nb, solid, ph.inv_sh, d);
+    read_pops<T, SH, QH, PAR>(h, (uint32_t)n, nb, solid, ph[PI_INV_SH], d);
     T s = T(0);
 #pragma unroll
     for (int i = 0; i < QH; ++i) s += d[i];
-    return ph.href + s;
+    return ph[PI_HREF] + s;
 }
 
 template <typename T, typename SH, int PAR>
@@ -334,6 +313,72 @@ __device__ inline T wave_max(T v) {
     return v;
 }
 
+// ------------------------------------------------------------ node state
+// Per-node quantities the D3Q19 and D3Q7 updates need once the moments are
+// known (all in the compute precision T).
+template <typename T> struct NodeState {
+    T u[3], uu, grad[3], ug, V[3], uV, rho, pdev, Pi[6], trPi, om, pc, tn[3];
+};
+
+// D3Q19 post-collision (MODE_STEP) or equilibrium (MODE_INIT) deviation of
+// direction i (Eqs. 6-8, 13-15, in the deviation form of the module notes):
+//   d*_i = w_i (rho gam_i + pdev) + K_i / 2 + om w_i (c c - T I):Pi
+//   g_eq_i - w_i gref = w_i (rho gam_i + pdev) - K_i / 2
+//   K_i = w_i gam_i rdif (c_i - u).grad + Gamma_i (c_i - u).V
+// with gam_i = Gamma_i / w_i - 1 and V = (mu grad + F) / T.
+template <typename T, int MODE>
+__device__ inline T g_out(int i, const NodeState<T>& s, T rdif) {
+    const T w = T(wg(i));
+    const T a = T(CX[i]) * s.u[0] + T(CY[i]) * s.u[1] + T(CZ[i]) * s.u[2];
+    const T gam = T(3) * a + T(4.5) * a * a - T(1.5) * s.uu;
+    const T cgr = T(CX[i]) * s.grad[0] + T(CY[i]) * s.grad[1] + T(CZ[i]) * s.grad[2] - s.ug;
+    const T cv = T(CX[i]) * s.V[0] + T(CY[i]) * s.V[1] + T(CZ[i]) * s.V[2] - s.uV;
+    const T K = w * (gam * rdif * cgr + (T(1) + gam) * cv);
+    const T base = w * (s.rho * gam + s.pdev);
+    if (MODE == MODE_INIT) return base - T(0.5) * K;
+    const T cPc = T(CX[i] * CX[i]) * s.Pi[0] + T(CY[i] * CY[i]) * s.Pi[1] + T(CZ[i] * CZ[i]) * s.Pi[2] +
+                  T(2 * CX[i] * CY[i]) * s.Pi[3] + T(2 * CX[i] * CZ[i]) * s.Pi[4] +
+                  T(2 * CY[i] * CZ[i]) * s.Pi[5];
+    return base + T(0.5) * K + s.om * w * (cPc - s.trPi);
+}
+
+// The same for the pair (i, opp(i)), sharing the terms even in c.
+template <typename T, int MODE>
+__device__ inline void g_out_pair(int i, const NodeState<T>& s, T rdif, T& vp, T& vm) {
+    const T w = T(wg(i));
+    const T a = T(CX[i]) * s.u[0] + T(CY[i]) * s.u[1] + T(CZ[i]) * s.u[2];
+    const T e = T(4.5) * a * a - T(1.5) * s.uu;
+    const T gp = e + T(3) * a, gm = e - T(3) * a;
+    const T b = T(CX[i]) * s.grad[0] + T(CY[i]) * s.grad[1] + T(CZ[i]) * s.grad[2];
+    const T c = T(CX[i]) * s.V[0] + T(CY[i]) * s.V[1] + T(CZ[i]) * s.V[2];
+    const T Kp = w * (gp * rdif * (b - s.ug) + (T(1) + gp) * (c - s.uV));
+    const T Km = w * (gm * rdif * (-b - s.ug) + (T(1) + gm) * (-c - s.uV));
+    const T bp = w * (s.rho * gp + s.pdev), bm = w * (s.rho * gm + s.pdev);
+    if (MODE == MODE_INIT) {
+        vp = bp - T(0.5) * Kp;
+        vm = bm - T(0.5) * Km;
+        return;
+    }
+    const T cPc = T(CX[i] * CX[i]) * s.Pi[0] + T(CY[i] * CY[i]) * s.Pi[1] + T(CZ[i] * CZ[i]) * s.Pi[2] +
+                  T(2 * CX[i] * CY[i]) * s.Pi[3] + T(2 * CX[i] * CZ[i]) * s.Pi[4] +
+                  T(2 * CY[i] * CZ[i]) * s.Pi[5];
+    const T filt = s.om * w * (cPc - s.trPi);
+    vp = bp + T(0.5) * Kp + filt;
+    vm = bm + T(0.5) * Km + filt;
+}
+
+// D3Q7 equilibrium deviation of the pair (i, opp(i)) (Eqs. 2-4):
+// h_eq_i - w_i href = w_i [(phi - href) + phi gam^h_i + theta c_i.n]
+template <typename T>
+__device__ inline void h_eq_pair(int i, const NodeState<T>& s, T href, T& hp, T& hm) {
+    const T w = T(wh(i));
+    const T a = T(CX[i]) * s.u[0] + T(CY[i]) * s.u[1] + T(CZ[i]) * s.u[2];
+    const T e = (s.pc - href) + s.pc * (T(8) * a * a - T(2) * s.uu);
+    const T o = s.pc * T(4) * a + (T(CX[i]) * s.tn[0] + T(CY[i]) * s.tn[1] + T(CZ[i]) * s.tn[2]);
+    hp = w * (e + o);
+    hm = w * (e - o);
+}
+
 #ifndef SWEEP_WAVES_PER_EU
 #define SWEEP_WAVES_PER_EU 1
 #endif
@@ -351,6 +396,7 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
     if (MODE == MODE_STEP && step >= uni(D->stop_step)) return;
     const int64_t time = step - uni(D->t0);
     const int nx = uni(D->nx), ny = uni(D->ny), nz = uni(D->nz);
+    const int nxy = nx * ny;
     constexpr int TY = NTHREADS / TX;
     const int tid = threadIdx.x;
     const int tx = tid & (TX - 1), ty = tid / TX;
@@ -364,23 +410,37 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
     const T* __restrict__ phig = unip((const T*)D->phi);
     const uint8_t* __restrict__ flg = unip(D->flag);
     const uint32_t* __restrict__ lnk = unip(D->link);
-    const PopArray<SH, QH> hb = pop_array<SH, QH>(D->h, uni(D->N));
-    const PopArray<SG, QG> gb = pop_array<SG, QG>(D->g, uni(D->N));
+    const PopArray<SH, QH> hb = pop_array<SH, QH>(D->h, N);
+    const PopArray<SG, QG> gb = pop_array<SG, QG>(D->g, N);
     const T Tg = T(TGc);
-    // exact reciprocals of the lattice temperatures: 1/Tg = 3, 1/(2 Tg) = 1.5,
-    // 1/(2 Tg^2) = 4.5, 1/Th = 4, 1/(2 Th) = 2, 1/(2 Th^2) = 8
-    const T iTg = T(3), i2Tg = T(1.5), i2Tg2 = T(4.5), iTh = T(4), i2Th = T(2), i2Th2 = T(8);
+    const T iTg = T(3), i2Tg2 = T(4.5);
+    const T rdif = ph[PI_RDIF];
 
+    // LDS ring of phi and flags: each plane holds the tile plus a one-node
+    // halo; a thread stages at most two cells, whose in-plane offsets (with
+    // the periodic wrap) are fixed for the whole z-march
     constexpr int LW = TX + 2, LN = (TX + 2) * (TY + 2);
-    static_assert(LN <= LDS_PLANE, "LDS plane too small");
+    static_assert(LN <= LDS_PLANE && LN <= 2 * NTHREADS, "LDS plane");
+    int coff0, coff1 = -1;
+    {
+        const int lx = tid % LW, ly = tid / LW;
+        coff0 = wrapc(tl.x0 - 1 + lx, nx) + nx * wrapc(tl.y0 - 1 + ly, ny);
+        const int c1 = tid + NTHREADS;
+        if (c1 < LN) {
+            const int lx1 = c1 % LW, ly1 = c1 / LW;
+            coff1 = wrapc(tl.x0 - 1 + lx1, nx) + nx * wrapc(tl.y0 - 1 + ly1, ny);
+        }
+    }
     auto stage = [&](int m, int zp) {
-        const int zz = wrapc(zp, nz);
-        for (int c = tid; c < LN; c += NTHREADS) {
-            const int lx = c % LW, ly = c / LW;
-            const int gx = wrapc(tl.x0 - 1 + lx, nx), gy = wrapc(tl.y0 - 1 + ly, ny);
-            const int n = gx + nx * (gy + ny * zz);
-            s_phi[m & 3][c] = phig[n];
-            s_flag[m & 3][c] = flg[n];
+        const int zz = zp < 0 ? zp + nz : (zp >= nz ? zp - nz : zp);
+        const int zo = zz * nxy;
+        if (tid < LN) {
+            s_phi[m & 3][tid] = phig[coff0 + zo];
+            s_flag[m & 3][tid] = flg[coff0 + zo];
+        }
+        if (coff1 >= 0) {
+            s_phi[m & 3][tid + NTHREADS] = phig[coff1 + zo];
+            s_flag[m & 3][tid + NTHREADS] = flg[coff1 + zo];
         }
     };
 
@@ -399,7 +459,7 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
         __syncthreads();
         if (!active) continue;
         const int sm = k & 3, s0 = (k + 1) & 3, sp = (k + 2) & 3;
-        const int n = x + nx * (y + ny * z);
+        const int n = x + nx * y + nxy * z;
         const uint8_t f = s_flag[s0][c0];
         const int kind = flag_kind(f);
         if (kind != KIND_FLUID) {
@@ -422,139 +482,142 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
         const uint32_t solid = links & SOLID_MASK;
         Nbr nb;
         nb.init(x, y, z, nx, ny, nz);
-
-        // ---- gradient and Laplacian (Eq. 16) over the 18 neighbours, with
-        //      the node's own phi standing in at solid links (pre-gradient)
+        NodeState<T> st;
         const T pc = s_phi[s0][c0];
-        T grad[3] = {T(0), T(0), T(0)}, lap = T(0);
+        st.pc = pc;
+
+        // ---- gradient and Laplacian (Eq. 16) over the 18 neighbours
+        T gx = T(0), gy = T(0), gz = T(0), lap = T(0);
 #pragma unroll
         for (int i = 1; i < 19; ++i) {
             const int sl = CZ[i] < 0 ? sm : (CZ[i] > 0 ? sp : s0);
-            T v = s_phi[sl][c0 + CY[i] * LW + CX[i]];
-            v = ((solid >> i) & 1u) ? pc : v;
-            grad[0] += T(wg(i) * CX[i]) * v;
-            grad[1] += T(wg(i) * CY[i]) * v;
-            grad[2] += T(wg(i) * CZ[i]) * v;
+            const T v = s_phi[sl][c0 + CY[i] * LW + CX[i]];
+            if (CX[i]) gx += T(wg(i) * CX[i]) * v;
+            if (CY[i]) gy += T(wg(i) * CY[i]) * v;
+            if (CZ[i]) gz += T(wg(i) * CZ[i]) * v;
             lap += T(wg(i)) * (v - pc);
         }
-        grad[0] *= iTg; grad[1] *= iTg; grad[2] *= iTg;
-        lap = T(6) * lap;
         T nw[3] = {T(0), T(0), T(0)};
         if (solid) {
-            // wetting (Eqs. 17-19): wall normal into the fluid from the solid
-            // links, t the unit tangential part of the pre-gradient,
-            // w = -cos(theta) n + sin(theta) t, phi_s,i from the tanh profile
-            // through phi(x) shifted by d_i = w . c_i; the stencil sums then
-            // take phi_s,i - phi(x) at each solid link
-#pragma unroll
-            for (int i = 1; i < 19; ++i) {
-                if ((solid >> i) & 1u) {
-                    nw[0] -= T(wg(i) * CX[i]);
-                    nw[1] -= T(wg(i) * CY[i]);
-                    nw[2] -= T(wg(i) * CZ[i]);
-                }
-            }
-            const T nn = dev_sqrt(nw[0] * nw[0] + nw[1] * nw[1] + nw[2] * nw[2]);
-            const T inn = nn > T(0) ? T(1) / nn : T(0);
-            nw[0] *= inn; nw[1] *= inn; nw[2] *= inn;
-            const T ng = nw[0] * grad[0] + nw[1] * grad[1] + nw[2] * grad[2];
-            T gt[3] = {grad[0] - nw[0] * ng, grad[1] - nw[1] * ng, grad[2] - nw[2] * ng};
-            const T tn = dev_sqrt(gt[0] * gt[0] + gt[1] * gt[1] + gt[2] * gt[2]);
-            const T itn = T(1) / (tn + ph.eps);
-            gt[0] *= itn; gt[1] *= itn; gt[2] *= itn;
-            T a = T(2) * pc - T(1);
-            a = a > T(1) - ph.clamp_a ? T(1) - ph.clamp_a : a;
-            a = a < -T(1) + ph.clamp_a ? -T(1) + ph.clamp_a : a;
-            const T k2W = T(2) / ph.W;
+            // wetting (Eqs. 17-19).  Pre-gradient with the node's own phi at
+            // the solid links; wall normal into the fluid from the solid links;
+            // w = -cos(theta) n + sin(theta) t with t the unit tangential part of
+            // the pre-gradient; phi_s,i from the tanh profile through phi(x)
+            // shifted by d_i = w . c_i; the stencil sums take phi_s,i there
             T dgx = T(0), dgy = T(0), dgz = T(0), dl = T(0);
             for (int i = 1; i < 19; ++i) {
                 if (!((solid >> i) & 1u)) continue;
                 const int cx = CX[i], cy = CY[i], cz = CZ[i];
                 const int sl = cz < 0 ? sm : (cz > 0 ? sp : s0);
+                const T d = T(wg(i)) * (pc - s_phi[sl][c0 + cy * LW + cx]);
+                dgx += d * T(cx); dgy += d * T(cy); dgz += d * T(cz);
+                dl += d;
+                nw[0] -= T(wg(i) * cx); nw[1] -= T(wg(i) * cy); nw[2] -= T(wg(i) * cz);
+            }
+            gx += dgx; gy += dgy; gz += dgz; lap += dl;
+            const T nn = dev_sqrt(nw[0] * nw[0] + nw[1] * nw[1] + nw[2] * nw[2]);
+            const T inn = nn > T(0) ? T(1) / nn : T(0);
+            nw[0] *= inn; nw[1] *= inn; nw[2] *= inn;
+            const T g0[3] = {gx * iTg, gy * iTg, gz * iTg};
+            const T ng = nw[0] * g0[0] + nw[1] * g0[1] + nw[2] * g0[2];
+            T gt[3] = {g0[0] - nw[0] * ng, g0[1] - nw[1] * ng, g0[2] - nw[2] * ng};
+            const T tnn = dev_sqrt(gt[0] * gt[0] + gt[1] * gt[1] + gt[2] * gt[2]);
+            const T itn = T(1) / (tnn + ph[PI_EPS]);
+            gt[0] *= itn; gt[1] *= itn; gt[2] *= itn;
+            T a = T(2) * pc - T(1);
+            a = a > T(1) - ph[PI_CLAMP_A] ? T(1) - ph[PI_CLAMP_A] : a;
+            a = a < -T(1) + ph[PI_CLAMP_A] ? -T(1) + ph[PI_CLAMP_A] : a;
+            const T k2W = ph[PI_K2W];
+            T egx = T(0), egy = T(0), egz = T(0), el = T(0);
+            for (int i = 1; i < 19; ++i) {
+                if (!((solid >> i) & 1u)) continue;
+                const int cx = CX[i], cy = CY[i], cz = CZ[i];
+                const int sl = cz < 0 ? sm : (cz > 0 ? sp : s0);
                 const int mat = flag_sub(s_flag[sl][c0 + cy * LW + cx]);
-                const T ct = (T)D->cos_t[mat], st = (T)D->sin_t[mat];
+                const T ct = (T)D->cos_t[mat], sn = (T)D->sin_t[mat];
                 const T d = -ct * (nw[0] * T(cx) + nw[1] * T(cy) + nw[2] * T(cz)) +
-                            st * (gt[0] * T(cx) + gt[1] * T(cy) + gt[2] * T(cz));
+                            sn * (gt[0] * T(cx) + gt[1] * T(cy) + gt[2] * T(cz));
                 const T t = dev_tanh(k2W * d);
                 // tanh(artanh(a) + 2d/W) by the addition theorem
                 const T ps = T(0.5) * (T(1) + (a + t) / (T(1) + a * t));
                 const T w = T(wg(i)) * (ps - pc);
-                dgx += w * T(cx); dgy += w * T(cy); dgz += w * T(cz);
-                dl += w;
+                egx += w * T(cx); egy += w * T(cy); egz += w * T(cz);
+                el += w;
             }
-            grad[0] += dgx * iTg; grad[1] += dgy * iTg; grad[2] += dgz * iTg;
-            lap += T(6) * dl;
+            gx += egx; gy += egy; gz += egz; lap += el;
         }
+        st.grad[0] = gx * iTg; st.grad[1] = gy * iTg; st.grad[2] = gz * iTg;
+        lap = T(6) * lap;
 
         // ---- local scalars (Eq. 9, Eqs. 10-12)
         const T pb = clamp01(pc);
-        const T rho = ph.rho_g + pb * ph.rdif;
-        const T mu = T(48) * ph.sigma / ph.W * pc * (pc - T(1)) * (pc - T(0.5)) -
-                     T(1.5) * ph.sigma * ph.W * lap;
+        st.rho = ph[PI_RHO_G] + pb * rdif;
+        const T mu = ph[PI_MU3] * pc * (pc - T(1)) * (pc - T(0.5)) - ph[PI_MULAP] * lap;
 
         // ---- moments of the populations entering the collision
-        T u[3], pdev;                       // pdev = P/T - gref
         T m[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};   // sum c c d: xx yy zz xy xz yz
         if (MODE == MODE_INIT) {
             const double* ui = in.u;
-            u[0] = ui ? (T)ui[n] : T(0);
-            u[1] = ui ? (T)ui[N + n] : T(0);
-            u[2] = ui ? (T)ui[2 * N + n] : T(0);
-            const T P0 = in.P ? (T)in.P[n] : (T)D->P_ref;
-            pdev = P0 * iTg - ph.gref;
+            st.u[0] = ui ? (T)ui[n] : T(0);
+            st.u[1] = ui ? (T)ui[N + n] : T(0);
+            st.u[2] = ui ? (T)ui[2 * N + n] : T(0);
+            st.pdev = in.P ? (T)in.P[n] * iTg - ph[PI_GREF] : ph[PI_PREF_DEV];
         } else {
             T dg[QG];
-            read_pops<T, SG, QG, PAR>(gb, (uint32_t)n, nb, solid, ph.inv_sg, dg);
-            // u first (it needs only g and phi), then P (after Eq. 15)
-            T s = T(0), j[3] = {T(0), T(0), T(0)};
+            read_pops<T, SG, QG, PAR>(gb, (uint32_t)n, nb, solid, ph[PI_INV_SG], dg);
+            // pairs (i, opp(i)): even part feeds mass and second moments, odd
+            // part the momentum; u first (it needs only g and phi), then P
+            T s = dg[0], j[3] = {T(0), T(0), T(0)};
 #pragma unroll
-            for (int i = 0; i < QG; ++i) {
-                s += dg[i];
-                j[0] += T(CX[i]) * dg[i];
-                j[1] += T(CY[i]) * dg[i];
-                j[2] += T(CZ[i]) * dg[i];
-                if (CX[i]) m[0] += dg[i];
-                if (CY[i]) m[1] += dg[i];
-                if (CZ[i]) m[2] += dg[i];
-                if (CX[i] * CY[i]) m[3] += T(CX[i] * CY[i]) * dg[i];
-                if (CX[i] * CZ[i]) m[4] += T(CX[i] * CZ[i]) * dg[i];
-                if (CY[i] * CZ[i]) m[5] += T(CY[i] * CZ[i]) * dg[i];
+            for (int i = 1; i < QG; i += 2) {
+                const T ev = dg[i] + dg[i + 1], od = dg[i] - dg[i + 1];
+                s += ev;
+                if (CX[i]) j[0] += T(CX[i]) * od;
+                if (CY[i]) j[1] += T(CY[i]) * od;
+                if (CZ[i]) j[2] += T(CZ[i]) * od;
+                if (CX[i]) m[0] += ev;
+                if (CY[i]) m[1] += ev;
+                if (CZ[i]) m[2] += ev;
+                if (CX[i] * CY[i]) m[3] += T(CX[i] * CY[i]) * ev;
+                if (CX[i] * CZ[i]) m[4] += T(CX[i] * CZ[i]) * ev;
+                if (CY[i] * CZ[i]) m[5] += T(CY[i] * CZ[i]) * ev;
             }
-            const T irho = T(1) / rho;
-            u[0] = (j[0] + T(0.5) * (mu * grad[0] + ph.F[0])) * irho;
-            u[1] = (j[1] + T(0.5) * (mu * grad[1] + ph.F[1])) * irho;
-            u[2] = (j[2] + T(0.5) * (mu * grad[2] + ph.F[2])) * irho;
-            pdev = s + T(0.5) * ph.rdif * (u[0] * grad[0] + u[1] * grad[1] + u[2] * grad[2]);
+            const T irho = T(1) / st.rho;
+            st.u[0] = (j[0] + T(0.5) * (mu * st.grad[0] + ph[PI_FX])) * irho;
+            st.u[1] = (j[1] + T(0.5) * (mu * st.grad[1] + ph[PI_FY])) * irho;
+            st.u[2] = (j[2] + T(0.5) * (mu * st.grad[2] + ph[PI_FZ])) * irho;
+            st.pdev = s + T(0.5) * rdif *
+                              (st.u[0] * st.grad[0] + st.u[1] * st.grad[1] + st.u[2] * st.grad[2]);
             if (MODE == MODE_READ && ro.pops) {
                 for (int i = 0; i < QG; ++i)
-                    ro.pops[(int64_t)(QH + i) * N + n] = (double)(T(wg(i)) * ph.gref + dg[i]);
+                    ro.pops[(int64_t)(QH + i) * N + n] = (double)(T(wg(i)) * ph[PI_GREF] + dg[i]);
             }
         }
-        const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+        st.uu = st.u[0] * st.u[0] + st.u[1] * st.u[1] + st.u[2] * st.u[2];
 
         if (MODE == MODE_READ) {
-            const T P = Tg * (ph.gref + pdev);
+            const T P = Tg * (ph[PI_GREF] + st.pdev);
             if (ro.phi) ro.phi[n] = (double)pc;
             if (ro.P) ro.P[n] = (double)P;
-            if (ro.u) { ro.u[n] = (double)u[0]; ro.u[N + n] = (double)u[1]; ro.u[2 * N + n] = (double)u[2]; }
+            if (ro.u) { ro.u[n] = (double)st.u[0]; ro.u[N + n] = (double)st.u[1]; ro.u[2 * N + n] = (double)st.u[2]; }
             if (ro.pops) {
                 T dh[QH];
-                read_pops<T, SH, QH, PAR>(hb, (uint32_t)n, nb, solid, ph.inv_sh, dh);
+                read_pops<T, SH, QH, PAR>(hb, (uint32_t)n, nb, solid, ph[PI_INV_SH], dh);
                 for (int i = 0; i < QH; ++i)
-                    ro.pops[(int64_t)i * N + n] = (double)(T(wh(i)) * ph.href + dh[i]);
+                    ro.pops[(int64_t)i * N + n] = (double)(T(wh(i)) * ph[PI_HREF] + dh[i]);
             }
         }
         if (DIAG && diag) {
-            const double um = sqrt((double)uu);
-            const double P = (double)(Tg * (ph.gref + pdev));
+            const double um = sqrt((double)st.uu);
+            const double P = (double)(Tg * (ph[PI_GREF] + st.pdev));
             const bool bad = isnan((double)pc) || isnan(um) || isnan(P);
             if (bad) {
                 acc[P_NAN] += 1.0;
             } else {
                 acc[P_PHI] += (double)pc;
-                acc[P_MX] += (double)(rho * u[0]);
-                acc[P_MY] += (double)(rho * u[1]);
-                acc[P_MZ] += (double)(rho * u[2]);
+                acc[P_MX] += (double)(st.rho * st.u[0]);
+                acc[P_MY] += (double)(st.rho * st.u[1]);
+                acc[P_MZ] += (double)(st.rho * st.u[2]);
                 acc[P_UMAX] = fmax(acc[P_UMAX], um);
                 if (pc > T(0.99)) { acc[P_PLIQ] += P; acc[P_NLIQ] += 1.0; }
                 if (pc < T(0.01)) { acc[P_PGAS] += P; acc[P_NGAS] += 1.0; }
@@ -563,163 +626,156 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
         if (MODE == MODE_READ) continue;
 
         // ---- D3Q19 filtered collision (Eqs. 6-8, 13-15) in moment space.
-        // With Gamma_i = w_i (1 + gam_i) and the equilibrium deviation
-        //   deq_i = rho w_i gam_i + w_i pdev - K_i / 2,
-        // the second moment of deq follows in closed form on D3Q19 (its weights
-        // are isotropic to fourth order):
+        // The second moment of the equilibrium deviation follows in closed
+        // form on D3Q19 (weights isotropic to fourth order):
         //   sum_i c c deq_i = rho u u + T pdev I - (1/2) sum_i c c K_i,
         //   sum_i c c K_i = rdif [T (u g + g u) - u u (u.g) + T I (u.g)]
-        //                 + (mu/T) [T (u g + g u) - u u (u.g)]
-        //                 + (1/T) [T (u F + F u) - u u (u.F)],   g = grad phi,
+        //                 + T (u V + V u) - u u (u.V),   g = grad phi,
         // so Pi = sum c c (d - deq) needs only the ten moments of the incoming
-        // populations, and every outgoing population is computed and stored
-        // on its own:  d*_i = deq_i + K_i + (1 - 1/tau) w_i/(2T^2) (c c - T I):Pi.
-        const T ug = u[0] * grad[0] + u[1] * grad[1] + u[2] * grad[2];
-        const T uF = u[0] * ph.F[0] + u[1] * ph.F[1] + u[2] * ph.F[2];
-        T om = T(0), Pi[6] = {T(0), T(0), T(0), T(0), T(0), T(0)}, trPi = T(0);
+        // populations, and each outgoing population is computed and stored
+        // on its own (g_out, g_out_pair).
+        st.ug = st.u[0] * st.grad[0] + st.u[1] * st.grad[1] + st.u[2] * st.grad[2];
+        st.V[0] = (mu * st.grad[0] + ph[PI_FX]) * iTg;
+        st.V[1] = (mu * st.grad[1] + ph[PI_FY]) * iTg;
+        st.V[2] = (mu * st.grad[2] + ph[PI_FZ]) * iTg;
+        st.uV = st.u[0] * st.V[0] + st.u[1] * st.V[1] + st.u[2] * st.V[2];
+        st.om = T(0);
+        st.trPi = T(0);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) st.Pi[c] = T(0);
         if (MODE == MODE_STEP) {
-            const T cg = ph.rdif + mu * iTg;              // coefficient of (u g + g u)
-            const T cu3 = (ph.rdif + mu * iTg) * ug + uF * iTg;   // coefficient of -u u
-            const T ciso = ph.rdif * Tg * ug;            // coefficient of I
-            // sum c c K: symmetric tensor, components xx yy zz xy xz yz
+            const T cuu = rdif * st.ug + st.uV;            // coefficient of -u u
+            const T ciso = rdif * Tg * st.ug;              // coefficient of I
             const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
 #pragma unroll
             for (int c = 0; c < 6; ++c) {
                 const int al = ia[c], be = ib[c];
-                const T ccK = cg * Tg * (u[al] * grad[be] + grad[al] * u[be]) +
-                              (u[al] * ph.F[be] + ph.F[al] * u[be]) -
-                              u[al] * u[be] * cu3 + (c < 3 ? ciso : T(0));
-                const T ccdeq = rho * u[al] * u[be] + (c < 3 ? Tg * pdev : T(0)) - T(0.5) * ccK;
-                Pi[c] = m[c] - ccdeq;
+                const T ccK = Tg * (rdif * (st.u[al] * st.grad[be] + st.grad[al] * st.u[be]) +
+                                    (st.u[al] * st.V[be] + st.V[al] * st.u[be])) -
+                              st.u[al] * st.u[be] * cuu + (c < 3 ? ciso : T(0));
+                const T ccdeq = st.rho * st.u[al] * st.u[be] + (c < 3 ? Tg * st.pdev : T(0)) -
+                                T(0.5) * ccK;
+                st.Pi[c] = m[c] - ccdeq;
             }
-            trPi = Tg * (Pi[0] + Pi[1] + Pi[2]);
+            st.trPi = Tg * (st.Pi[0] + st.Pi[1] + st.Pi[2]);
             T Fm;
-            if (ph.mix) Fm = T(0.5) * (dev_tanh((pb - ph.mix_phi) * ph.mix_invw) + T(1));
+            if (ph.mix) Fm = T(0.5) * (dev_tanh((pb - ph[PI_MIX_PHI]) * ph[PI_MIX_INVW]) + T(1));
             else Fm = pb;
-            const T tau = (T(1) - Fm) * ph.tau_g + Fm * ph.tau_l;
-            om = (T(1) - T(1) / tau) * i2Tg2;
+            const T tau = (T(1) - Fm) * ph[PI_TAU_G] + Fm * ph[PI_TAU_L];
+            st.om = (T(1) - T(1) / tau) * i2Tg2;
         }
-        // bounce-back of the moving-wall kind inside the free-slip band
-        // (Sec. III.A): the wall moves with the tangential fluid velocity
-        T uw[3] = {T(0), T(0), T(0)};
-        if (MODE == MODE_STEP && solid && ph.friction && pc >= ph.slip_lo && pc <= ph.slip_hi) {
-            const T un = nw[0] * u[0] + nw[1] * u[1] + nw[2] * u[2];
-            uw[0] = u[0] - nw[0] * un;
-            uw[1] = u[1] - nw[1] * un;
-            uw[2] = u[2] - nw[2] * un;
-        }
-#pragma unroll
-        for (int i = 0; i < QG; ++i) {
-            const T w = T(wg(i));
-            const T cu = T(CX[i]) * u[0] + T(CY[i]) * u[1] + T(CZ[i]) * u[2];
-            const T gam = cu * iTg + cu * cu * i2Tg2 - uu * i2Tg;  // Gamma/w - 1
-            const T G = w * (T(1) + gam);
-            const T cgr = T(CX[i]) * grad[0] + T(CY[i]) * grad[1] + T(CZ[i]) * grad[2] - ug;
-            const T cf = T(CX[i]) * ph.F[0] + T(CY[i]) * ph.F[1] + T(CZ[i]) * ph.F[2] - uF;
-            const T K = (w * gam * ph.rdif + G * mu * iTg) * cgr + G * cf * iTg;
-            const T base = w * (rho * gam + pdev);
-            T v;
+        // D3Q19 write-back (AA slots of parity PAR)
+        const T sg = ph[PI_SG];
+        auto put_g = [&](int i, T v) {
+            const T vs = Store<SG>::scaled ? v * sg : v;
             if (MODE == MODE_STEP) {
-                const T cPc = T(CX[i] * CX[i]) * Pi[0] + T(CY[i] * CY[i]) * Pi[1] +
-                              T(CZ[i] * CZ[i]) * Pi[2] + T(2 * CX[i] * CY[i]) * Pi[3] +
-                              T(2 * CX[i] * CZ[i]) * Pi[4] + T(2 * CY[i] * CZ[i]) * Pi[5];
-                v = base + T(0.5) * K + om * w * (cPc - trPi);
-                const T vs = Store<SG>::scaled ? v * ph.sg : v;
-                if (PAR == 0 || i == 0) {
-                    T vb = vs;
-                    if (i > 0 && ((solid >> i) & 1u)) {
-                        const T cuw = T(CX[i]) * uw[0] + T(CY[i]) * uw[1] + T(CZ[i]) * uw[2];
-                        const T vw = v - T(6) * w * rho * cuw;
-                        vb = Store<SG>::scaled ? vw * ph.sg : vw;
-                    }
-                    Store<SG>::st(gb, OPP[i], (uint32_t)n, vb);
-                } else {
-                    Store<SG>::st(gb, i, nb.at(CX[i], CY[i], CZ[i]), vs);
-                    if ((solid >> i) & 1u) {
-                        const T cuw = T(CX[i]) * uw[0] + T(CY[i]) * uw[1] + T(CZ[i]) * uw[2];
-                        const T vw = v - T(6) * w * rho * cuw;
-                        Store<SG>::st(gb, OPP[i], (uint32_t)n, Store<SG>::scaled ? vw * ph.sg : vw);
-                    }
-                }
+                if (PAR == 0 || i == 0) Store<SG>::st(gb, OPP[i], (uint32_t)n, vs);
+                else Store<SG>::st(gb, i, nb.at(CX[i], CY[i], CZ[i]), vs);
             } else {
-                v = base - T(0.5) * K;    // MODE_INIT: the equilibrium g_eq_i - w_i gref
-                const T vs = Store<SG>::scaled ? v * ph.sg : v;
-                if (PAR == 0 || i == 0) {
-                    Store<SG>::st(gb, i, (uint32_t)n, vs);
-                } else {
-                    Store<SG>::st(gb, OPP[i], nb.at(-CX[i], -CY[i], -CZ[i]), vs);
-                    if ((solid >> OPP[i]) & 1u) Store<SG>::st(gb, i, (uint32_t)n, vs);
-                }
+                if (PAR == 0 || i == 0) Store<SG>::st(gb, i, (uint32_t)n, vs);
+                else Store<SG>::st(gb, OPP[i], nb.at(-CX[i], -CY[i], -CZ[i]), vs);
             }
+        };
+        put_g(0, g_out<T, MODE>(0, st, rdif));
+#pragma unroll
+        for (int i = 1; i < QG; i += 2) {
+            T vp, vm;
+            g_out_pair<T, MODE>(i, st, rdif, vp, vm);
+            put_g(i, vp);
+            put_g(i + 1, vm);
         }
 
         // ---- D3Q7 phase field (Eqs. 1-5)
         {
-            const T gnorm = dev_sqrt(grad[0] * grad[0] + grad[1] * grad[1] + grad[2] * grad[2]);
-            T theta = ph.M * iTh * (T(1) - T(4) * (pc - T(0.5)) * (pc - T(0.5))) / ph.W;
+            const T gnorm = dev_sqrt(st.grad[0] * st.grad[0] + st.grad[1] * st.grad[1] +
+                                     st.grad[2] * st.grad[2]);
+            T theta = ph[PI_THETA0] * (T(1) - T(4) * (pc - T(0.5)) * (pc - T(0.5)));
             if (ph.mobility_corr) {
-                const T sgn = lap / (fabs(lap) + ph.eps);
-                const T y1a = clamp01((pc - ph.mc_phi_M) * ph.mc_invD);
-                const T y1b = clamp01((T(1) - pc) * ph.mc_invD);
-                const T y2a = clamp01(pc * ph.mc_invD);
-                const T y2b = clamp01((ph.mc_phi_m - pc) * ph.mc_invD);
+                const T sgn = lap / (fabs(lap) + ph[PI_EPS]);
+                const T y1a = clamp01((pc - ph[PI_MC_PHI_M]) * ph[PI_MC_INVD]);
+                const T y1b = clamp01((T(1) - pc) * ph[PI_MC_INVD]);
+                const T y2a = clamp01(pc * ph[PI_MC_INVD]);
+                const T y2b = clamp01((ph[PI_MC_PHI_m] - pc) * ph[PI_MC_INVD]);
                 const T Y1 = y1a < y1b ? y1a : y1b;
                 const T Y2 = y2a < y2b ? y2a : y2b;
-                theta += ph.mc_gamma * ph.M * iTh / ph.W * gnorm *
-                         ((T(1) + sgn) * Y1 + (T(1) - sgn) * Y2);
+                theta += ph[PI_MC_K] * gnorm * ((T(1) + sgn) * Y1 + (T(1) - sgn) * Y2);
             }
-            const T ign = theta / (gnorm + ph.eps);   // theta n = theta grad / (|grad| + eps)
-            const T tn[3] = {grad[0] * ign, grad[1] * ign, grad[2] * ign};
-            const T itau_h = T(1) / (ph.M * iTh + T(0.5));
+            const T ign = theta / (gnorm + ph[PI_EPS]);   // theta n = theta grad / (|grad| + eps)
+            st.tn[0] = st.grad[0] * ign; st.tn[1] = st.grad[1] * ign; st.tn[2] = st.grad[2] * ign;
+            const T href = ph[PI_HREF];
             T B[QH];
-            if (MODE == MODE_STEP) read_pops<T, SH, QH, PAR>(hb, (uint32_t)n, nb, solid, ph.inv_sh, B);
-#pragma unroll
-            for (int i = 0; i < QH; ++i) {
-                const T w = T(wh(i));
-                const T cu = T(CX[i]) * u[0] + T(CY[i]) * u[1] + T(CZ[i]) * u[2];
-                const T gam = cu * iTh + cu * cu * i2Th2 - uu * i2Th;
-                const T cn = T(CX[i]) * tn[0] + T(CY[i]) * tn[1] + T(CZ[i]) * tn[2];
-                const T heq = w * ((pc - ph.href) + pc * gam + cn);
-                if (MODE == MODE_STEP) B[i] = B[i] - (B[i] - heq) * itau_h;
-                else B[i] = heq;
+            if (MODE == MODE_STEP) read_pops<T, SH, QH, PAR>(hb, (uint32_t)n, nb, solid, ph[PI_INV_SH], B);
+            const T itau_h = ph[PI_ITAU_H];
+            {
+                const T heq0 = T(wh(0)) * ((pc - href) + pc * (-T(2) * st.uu));
+                B[0] = MODE == MODE_STEP ? B[0] + (heq0 - B[0]) * itau_h : heq0;
             }
-            if (MODE == MODE_STEP) write_pops<T, SH, QH, PAR>(hb, (uint32_t)n, nb, solid, ph.sh, B);
-            else place_pops<T, SH, QH, PAR>(hb, (uint32_t)n, nb, solid, ph.sh, B);
+#pragma unroll
+            for (int i = 1; i < QH; i += 2) {
+                T hp, hm;
+                h_eq_pair<T>(i, st, href, hp, hm);
+                if (MODE == MODE_STEP) {
+                    B[i] = B[i] + (hp - B[i]) * itau_h;
+                    B[i + 1] = B[i + 1] + (hm - B[i + 1]) * itau_h;
+                } else {
+                    B[i] = hp;
+                    B[i + 1] = hm;
+                }
+            }
+            if (MODE == MODE_STEP) write_pops<T, SH, QH, PAR>(hb, (uint32_t)n, nb, solid, ph[PI_SH], B);
+            else place_pops<T, SH, QH, PAR>(hb, (uint32_t)n, nb, solid, ph[PI_SH], B);
         }
-        if (MODE == MODE_INIT) continue;
 
-        // ---- pressure ghosts owned by this node: equilibria for step t+1 at
-        //      the owner's phi and u and the face pressure of step t+1, into
-        //      the slots the next (opposite) parity reads
-        if (links >> LINK_OWNER_SHIFT) {
+        // ---- solid links (Sec. III.A).  Half-way bounce-back returns the
+        //      population to the node's own slot: the odd step wrote it to the
+        //      solid node's slot above (never read), so it is written again;
+        //      the even step already wrote it to the own slot.  Inside the
+        //      free-slip band the wall moves with the tangential fluid velocity
+        //      (moving-wall bounce-back), which changes the returned g.
+        if (solid) {
+            if (MODE == MODE_STEP) {
+                T uw[3] = {T(0), T(0), T(0)};
+                bool slip = false;
+                if (ph.friction && pc >= ph[PI_SLIP_LO] && pc <= ph[PI_SLIP_HI]) {
+                    const T un = nw[0] * st.u[0] + nw[1] * st.u[1] + nw[2] * st.u[2];
+                    uw[0] = st.u[0] - nw[0] * un;
+                    uw[1] = st.u[1] - nw[1] * un;
+                    uw[2] = st.u[2] - nw[2] * un;
+                    slip = true;
+                }
+                if (PAR == 1 || slip) {
+                    for (int i = 1; i < QG; ++i) {
+                        if (!((solid >> i) & 1u)) continue;
+                        const T cuw = T(CX[i]) * uw[0] + T(CY[i]) * uw[1] + T(CZ[i]) * uw[2];
+                        const T v = g_out<T, MODE>(i, st, rdif) - T(6 * wg(i)) * st.rho * cuw;
+                        Store<SG>::st(gb, OPP[i], (uint32_t)n, Store<SG>::scaled ? v * sg : v);
+                    }
+                }
+            } else if (PAR == 1) {
+                // initial populations: f_i(x) also lands in the own slot when
+                // x - c_i is solid
+                for (int i = 1; i < QG; ++i) {
+                    if (!((solid >> OPP[i]) & 1u)) continue;
+                    const T v = g_out<T, MODE>(i, st, rdif);
+                    Store<SG>::st(gb, i, (uint32_t)n, Store<SG>::scaled ? v * sg : v);
+                }
+            }
+        }
+
+        // ---- pressure ghosts owned by this node: hand this step's u to the
+        //      ghost pass (phi of the owner already sits in the ghost's phi entry)
+        if (MODE == MODE_STEP && (links >> LINK_OWNER_SHIFT)) {
+            T* __restrict__ gbuf = (T*)D->gbuf;
+            const int64_t gc = D->gface_count;
             for (int face = 0; face < 6; ++face) {
                 if (!((links >> (LINK_OWNER_SHIFT + face)) & 1u)) continue;
                 const int ax = face >> 1, sgn = (face & 1) ? -1 : 1;   // inward normal
-                const int nfx = ax == 0 ? sgn : 0, nfy = ax == 1 ? sgn : 0, nfz = ax == 2 ? sgn : 0;
-                const uint32_t gidx = nb.at(-nfx, -nfy, -nfz);         // the ghost
-                const T Pb = (T)(D->face_P[face] + D->face_ramp[face] * (double)(time + 1));
-                const T pdb = Pb * iTg - ph.gref;
-#pragma unroll
-                for (int i = 1; i < QG; ++i) {
-                    if (CX[i] * nfx + CY[i] * nfy + CZ[i] * nfz <= 0) continue;
-                    // fluid node y = g + c_i = x + (c_i - n_f), inside the LDS ring
-                    const int ex = CX[i] - nfx, ey = CY[i] - nfy, ez = CZ[i] - nfz;
-                    const int sl = ez < 0 ? sm : (ez > 0 ? sp : s0);
-                    if (flag_kind(s_flag[sl][c0 + ey * LW + ex]) != KIND_FLUID) continue;
-                    const T cu = T(CX[i]) * u[0] + T(CY[i]) * u[1] + T(CZ[i]) * u[2];
-                    const uint32_t dst = PAR ? nb.at(ex, ey, ez) : gidx;
-                    const int slot = PAR ? i : OPP[i];
-                    {
-                        const T gam = cu * iTg + cu * cu * i2Tg2 - uu * i2Tg;
-                        const T v = T(wg(i)) * (rho * gam + pdb);
-                        Store<SG>::st(gb, slot, dst, Store<SG>::scaled ? v * ph.sg : v);
-                    }
-                    if (i < QH) {
-                        const T gam = cu * iTh + cu * cu * i2Th2 - uu * i2Th;
-                        const T v = T(wh(i)) * ((pc - ph.href) + pc * gam);
-                        Store<SH>::st(hb, slot, dst, Store<SH>::scaled ? v * ph.sh : v);
-                    }
-                }
+                const int gx2 = x - (ax == 0 ? sgn : 0), gy2 = y - (ax == 1 ? sgn : 0),
+                          gz2 = z - (ax == 2 ? sgn : 0);
+                const int64_t slot = ghost_slot(D->gface_base, face, gx2, gy2, gz2, nx, ny);
+                gbuf[slot] = st.u[0];
+                gbuf[gc + slot] = st.u[1];
+                gbuf[2 * gc + slot] = st.u[2];
             }
         }
     }
@@ -818,9 +874,78 @@ restore_kernel(const Desc* __restrict__ descs, const Tile* __restrict__ tiles,
         T dh[QH], dg[QG];
         for (int i = 0; i < QH; ++i) dh[i] = (T)(pops[(int64_t)i * N + n] - wh(i) * D->href);
         for (int i = 0; i < QG; ++i) dg[i] = (T)(pops[(int64_t)(QH + i) * N + n] - wg(i) * D->gref);
-        place_pops<T, SH, QH, PAR>(hb, (uint32_t)n, nb, solid, ph.sh, dh);
-        place_pops<T, SG, QG, PAR>(gb, (uint32_t)n, nb, solid, ph.sg, dg);
+        place_pops<T, SH, QH, PAR>(hb, (uint32_t)n, nb, solid, ph[PI_SH], dh);
+        place_pops<T, SG, QG, PAR>(gb, (uint32_t)n, nb, solid, ph[PI_SG], dg);
     }
+}
+
+// ---------------------------------------------------------- pressure ghosts
+// For every ghost g of a pressure face (Sec. III.A: Dirichlet P, Neumann u and
+// phi): the populations it hands to the fluid at the next step t+1 are the
+// equilibria at its owner's phi and u of step t and the face pressure of step
+// t+1, without forcing and without the counter-term.  Only the directions
+// that point into a fluid node are written, into the slots the next step's
+// parity reads: (g + c_i, i) for an even step, (g, opp(i)) for an odd one.
+// Runs after the sweep, which has advanced the step counter to t+1.
+template <typename T, typename SH, typename SG>
+__global__ void __launch_bounds__(NTHREADS)
+ghost_kernel(const Desc* __restrict__ descs, const GhostRef* __restrict__ ghosts, int nghosts) {
+    const int k = blockIdx.x * NTHREADS + threadIdx.x;
+    if (k >= nghosts) return;
+    const GhostRef gr = ghosts[k];
+    const Desc* D = descs + gr.lat;
+    const int64_t next = D->step;                 // step t+1
+    const int par = (int)(next & 1);
+    const int nx = D->nx, ny = D->ny, nz = D->nz;
+    const int64_t N = D->N;
+    const int g = gr.node;
+    const int x = g % nx, y = (g / nx) % ny, z = g / (nx * ny);
+    const uint8_t fg = D->flag[g];
+    const int face = flag_sub(fg);
+    const int ax = face >> 1, sgn = (face & 1) ? -1 : 1;
+    const int nfx = ax == 0 ? sgn : 0, nfy = ax == 1 ? sgn : 0, nfz = ax == 2 ? sgn : 0;
+    const T* pp = param_block<T>(D);
+    const T pc = ((const T*)D->phi)[g];           // the owner's phi (Neumann copy)
+    const int64_t slot = ghost_slot(D->gface_base, face, x, y, z, nx, ny);
+    const T* gb = (const T*)D->gbuf;
+    const int64_t gc = D->gface_count;
+    const T u[3] = {gb[slot], gb[gc + slot], gb[2 * gc + slot]};
+    const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const T pb = clamp01(pc);
+    const T rho = pp[PI_RHO_G] + pb * pp[PI_RDIF];
+    const double Pb = D->face_P[face] + D->face_ramp[face] * (double)(next - D->t0);
+    const T pdb = (T)(Pb * 3.0) - pp[PI_GREF];
+    const T iTg = T(3), i2Tg = T(1.5), i2Tg2 = T(4.5), iTh = T(4), i2Th = T(2), i2Th2 = T(8);
+    Nbr nb;
+    nb.init(x, y, z, nx, ny, nz);
+    // a launch may mix lattices, so the per-direction bases are per lane here
+    SG* const* gq = (SG* const*)D->gq;
+    SH* const* hq = (SH* const*)D->hq;
+#pragma unroll
+    for (int i = 1; i < QG; ++i) {
+        if (CX[i] * nfx + CY[i] * nfy + CZ[i] * nfz <= 0) continue;
+        const uint32_t y_n = nb.at(CX[i], CY[i], CZ[i]);   // g + c_i
+        if (flag_kind(D->flag[y_n]) != KIND_FLUID) continue;
+        const uint32_t dst = par == 0 ? y_n : (uint32_t)g;
+        const int q = par == 0 ? i : OPP[i];
+        const T cu = T(CX[i]) * u[0] + T(CY[i]) * u[1] + T(CZ[i]) * u[2];
+        const T gam = cu * iTg + cu * cu * i2Tg2 - uu * i2Tg;
+        const T vg = T(wg(i)) * (rho * gam + pdb);
+        gq[q][dst] = (SG)(Store<SG>::scaled ? vg * pp[PI_SG] : vg);
+        if (i < QH) {
+            const T gh = cu * iTh + cu * cu * i2Th2 - uu * i2Th;
+            const T vh = T(wh(i)) * ((pc - pp[PI_HREF]) + pc * gh);
+            hq[q][dst] = (SH)(Store<SH>::scaled ? vh * pp[PI_SH] : vh);
+        }
+    }
+}
+
+template <typename T, typename SH, typename SG>
+hipError_t launch_ghosts_storage(const Desc* d, const GhostRef* ghosts, int nghosts, hipStream_t s) {
+    if (nghosts <= 0) return hipSuccess;
+    dim3 grid((nghosts + NTHREADS - 1) / NTHREADS), block(NTHREADS);
+    ghost_kernel<T, SH, SG><<<grid, block, 0, s>>>(d, ghosts, nghosts);
+    return hipGetLastError();
 }
 
 // -------------------------------------------------------------- launchers

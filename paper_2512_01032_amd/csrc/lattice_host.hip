@@ -114,10 +114,24 @@ int choose_tz(const lbm_params* p, int tx) {
     return std::min(tz, p->nz);
 }
 
-static void layout_offsets(const lbm_params* p, int64_t ntiles, LatticeLayout* L) {
+static void face_planes(const lbm_params* p, LatticeLayout* L) {
+    int64_t b = 0;
+    for (int f = 0; f < 6; ++f) {
+        L->gface_base[f] = b;
+        if (p->face_bc[f] != LBM_BC_PRESSURE) continue;
+        const int ax = f / 2;
+        b += ax == 0 ? (int64_t)p->ny * p->nz : (ax == 1 ? (int64_t)p->nx * p->nz
+                                                         : (int64_t)p->nx * p->ny);
+    }
+    L->gface_count = b;
+}
+
+static void layout_offsets(const lbm_params* p, int64_t ntiles, int64_t nghosts,
+                           LatticeLayout* L) {
     int sh, sg, sphi;
     storage_sizes(p->storage, &sh, &sg, &sphi);
     const int64_t N = L->N;
+    face_planes(p, L);
     size_t o = 0;
     L->off_desc = o; o = align256(o + sizeof(Desc));
     L->off_counter = o; o = align256(o + sizeof(unsigned int));
@@ -128,6 +142,8 @@ static void layout_offsets(const lbm_params* p, int64_t ntiles, LatticeLayout* L
     L->off_link = o; o = align256(o + (size_t)N * 4);
     L->off_tiles = o; o = align256(o + (size_t)ntiles * sizeof(Tile));
     L->off_partials = o; o = align256(o + (size_t)ntiles * NPART * sizeof(double));
+    L->off_gbuf = o; o = align256(o + (size_t)3 * L->gface_count * sphi);
+    L->off_ghosts = o; o = align256(o + (size_t)nghosts * sizeof(GhostRef));
     L->total = o;
 }
 
@@ -138,7 +154,8 @@ size_t footprint_bytes(const lbm_params* p) {
     const int tx = choose_tx(p->nx), ty = NTHREADS / tx, tz = choose_tz(p, tx);
     const int64_t ntiles = (int64_t)((p->nx + tx - 1) / tx) * ((p->ny + ty - 1) / ty) *
                            ((p->nz + tz - 1) / tz);
-    layout_offsets(p, ntiles, &L);
+    face_planes(p, &L);
+    layout_offsets(p, ntiles, L.gface_count, &L);   // ghosts <= face entries
     return L.total;
 }
 
@@ -194,20 +211,29 @@ int build_layout(const lbm_params* p, const lbm_geometry* geo, int lat, LatticeL
                     set_error("pressure ghost (%d,%d,%d): its inward neighbour must be fluid", x, y, z);
                     return LBM_E_INVAL;
                 }
+                L->ghosts.push_back(GhostRef{lat, (int32_t)n});
                 L->flag[o] |= F_OWNER;
                 L->link[o] |= 1u << (LINK_OWNER_SHIFT + face);
             }
     // solid links of fluid nodes
-    for (int z = 0; z < nz; ++z)
-        for (int y = 0; y < ny; ++y)
+    for (int z = 0; z < nz; ++z) {
+        const int64_t Z[3] = {(int64_t)((z + nz - 1) % nz) * nx * ny, (int64_t)z * nx * ny,
+                              (int64_t)((z + 1) % nz) * nx * ny};
+        for (int y = 0; y < ny; ++y) {
+            const int64_t Y[3] = {(int64_t)((y + ny - 1) % ny) * nx, (int64_t)y * nx,
+                                  (int64_t)((y + 1) % ny) * nx};
             for (int x = 0; x < nx; ++x) {
-                const int64_t n = x + (int64_t)nx * (y + (int64_t)ny * z);
+                const int64_t n = x + Y[1] + Z[1];
                 if (flag_kind(L->flag[n]) != KIND_FLUID) continue;
+                const int64_t X[3] = {(x + nx - 1) % nx, x, (x + 1) % nx};
                 uint32_t m = 0;
                 for (int i = 1; i < 19; ++i)
-                    if (flag_kind(L->flag[idx(x + HCX[i], y + HCY[i], z + HCZ[i])]) == KIND_SOLID) m |= 1u << i;
+                    if (flag_kind(L->flag[X[HCX[i] + 1] + Y[HCY[i] + 1] + Z[HCZ[i] + 1]]) == KIND_SOLID)
+                        m |= 1u << i;
                 if (m) { L->link[n] |= m; L->flag[n] |= F_NEAR_WALL; }
             }
+        }
+    }
     // tile table: keep tiles holding at least one non-solid node
     const int tx = choose_tx(nx), ty = NTHREADS / tx, tz = choose_tz(p, tx);
     L->tx = tx; L->ty = ty; L->tz = tz;
@@ -228,7 +254,7 @@ int build_layout(const lbm_params* p, const lbm_geometry* geo, int lat, LatticeL
                 t.tile_in_lat = (int)L->tiles.size();
                 L->tiles.push_back(t);
             }
-    layout_offsets(p, (int64_t)L->tiles.size(), L);
+    layout_offsets(p, (int64_t)L->tiles.size(), (int64_t)L->ghosts.size(), L);
     return LBM_OK;
 }
 
@@ -251,6 +277,9 @@ void fill_desc(const lbm_params* p, const lbm_geometry* geo, const LatticeLayout
     d->flag = (const uint8_t*)(base + L.off_flag);
     d->link = (const uint32_t*)(base + L.off_link);
     d->partials = (double*)(base + L.off_partials);
+    d->gbuf = base + L.off_gbuf;
+    for (int f = 0; f < 6; ++f) d->gface_base[f] = L.gface_base[f];
+    d->gface_count = L.gface_count;
     d->counter = (unsigned int*)(base + L.off_counter);
     d->step = step;
     d->t0 = 0;
@@ -278,7 +307,7 @@ void fill_desc(const lbm_params* p, const lbm_geometry* geo, const LatticeLayout
         d->sin_t[k] = sin(th);
     }
     const bool shifted = p->storage >= ST_FP32_SHIFT;
-    d->clamp_a = p->storage == ST_FP64 ? 1e-12 : 1e-6;
+    d->clamp_a = p->storage == ST_FP64 ? 1e-12 : 1.2e-7;
     d->href = shifted ? 0.5 : 0.0;
     d->gref = shifted ? p->P_ref * 3.0 : 0.0;
     const int ksh = p->fp16_log2_scale_h ? p->fp16_log2_scale_h : 3;
@@ -286,6 +315,43 @@ void fill_desc(const lbm_params* p, const lbm_geometry* geo, const LatticeLayout
     d->scale_h = p->storage == ST_FP16_ALL ? ldexp(1.0, ksh) : 1.0;
     d->scale_g = p->storage >= ST_FP16_G ? ldexp(1.0, ksg) : 1.0;
     d->u_max = p->u_max;
+    // derived constants (Eq. 4 theta coefficient, Eq. 5 correction factor,
+    // Eq. 9 chemical-potential coefficients, Eqs. 10-12 relaxation times)
+    const double TG = 1.0 / 3.0, TH = 0.25;
+    double v[PI_COUNT];
+    v[PI_RHO_G] = p->rho_g;
+    v[PI_RDIF] = p->rho_l - p->rho_g;
+    v[PI_MU3] = 48.0 * p->sigma / p->W;
+    v[PI_MULAP] = 1.5 * p->sigma * p->W;
+    v[PI_TAU_G] = p->nu_g / TG + 0.5;
+    v[PI_TAU_L] = p->nu_l / TG + 0.5;
+    v[PI_THETA0] = p->M / TH / p->W;
+    v[PI_MC_K] = p->mobility_corr ? p->mc_gamma * p->M / (TH * p->W) : 0.0;
+    v[PI_MC_INVD] = 1.0 / d->mc_D;
+    v[PI_MC_PHI_M] = p->mc_phi_M;
+    v[PI_MC_PHI_m] = p->mc_phi_m;
+    v[PI_EPS] = p->eps;
+    v[PI_MIX_PHI] = p->mix_phi;
+    v[PI_MIX_INVW] = 1.0 / d->mix_width;
+    v[PI_SLIP_LO] = p->slip_lo;
+    v[PI_SLIP_HI] = p->slip_hi;
+    v[PI_CLAMP_A] = d->clamp_a;
+    v[PI_HREF] = d->href;
+    v[PI_GREF] = d->gref;
+    v[PI_SH] = d->scale_h;
+    v[PI_SG] = d->scale_g;
+    v[PI_INV_SH] = 1.0 / d->scale_h;
+    v[PI_INV_SG] = 1.0 / d->scale_g;
+    v[PI_ITAU_H] = 1.0 / (p->M / TH + 0.5);
+    v[PI_FX] = p->F_ex[0];
+    v[PI_FY] = p->F_ex[1];
+    v[PI_FZ] = p->F_ex[2];
+    v[PI_K2W] = 2.0 / p->W;
+    v[PI_PREF_DEV] = p->P_ref / TG - d->gref;
+    for (int k = 0; k < PI_COUNT; ++k) {
+        d->pd[k] = v[k];
+        d->pf[k] = (float)v[k];
+    }
 }
 
 #define HIPCHK(expr)                                                              \
@@ -311,6 +377,11 @@ int upload_and_init(const lbm_params* p, const lbm_geometry* geo, const lbm_init
     HIPCHK(hipMemcpyAsync(base + L.off_link, L.link.data(), (size_t)N * 4, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(base + L.off_tiles, L.tiles.data(), L.tiles.size() * sizeof(Tile),
                           hipMemcpyHostToDevice, s));
+    if (!L.ghosts.empty())
+        HIPCHK(hipMemcpyAsync(base + L.off_ghosts, L.ghosts.data(), L.ghosts.size() * sizeof(GhostRef),
+                              hipMemcpyHostToDevice, s));
+    if (L.gface_count)
+        HIPCHK(hipMemsetAsync(base + L.off_gbuf, 0, (size_t)3 * L.gface_count * sphi, s));
     const int64_t step0 = (init && init->kind == LBM_INIT_POPULATIONS) ? init->step : 0;
     fill_desc(p, geo, L, base, step0, hdesc);
     HIPCHK(hipMemcpyAsync(base + L.off_desc, hdesc, sizeof(Desc), hipMemcpyHostToDevice, s));

@@ -20,10 +20,13 @@ struct LatticeLayout {
     int64_t N = 0;
     int64_t n_fluid = 0, n_ghost = 0, n_solid = 0;
     size_t off_desc = 0, off_counter = 0, off_h = 0, off_g = 0, off_phi = 0, off_flag = 0,
-           off_link = 0, off_tiles = 0, off_partials = 0, total = 0;
+           off_link = 0, off_tiles = 0, off_partials = 0, off_gbuf = 0, off_ghosts = 0, total = 0;
+    int64_t gface_base[6] = {0, 0, 0, 0, 0, 0};
+    int64_t gface_count = 0;      // face-buffer entries (per velocity component)
     std::vector<uint8_t> flag;
     std::vector<uint32_t> link;
     std::vector<Tile> tiles;
+    std::vector<GhostRef> ghosts;
 };
 
 // Validate parameters (and geometry when given).  Returns LBM_OK or sets the

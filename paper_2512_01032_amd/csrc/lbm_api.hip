@@ -24,6 +24,8 @@ struct lbm_handle {
     Desc* ddesc = nullptr;
     Tile* dtiles = nullptr;
     int ntiles = 0;
+    GhostRef* dghosts = nullptr;
+    int nghosts = 0;
     int64_t step = 0;            // steps queued so far
     // stability flag copied back asynchronously after each lbm_step
     int* h_unstable = nullptr;   // pinned
@@ -107,6 +109,8 @@ extern "C" int lbm_create(const lbm_params* p, const lbm_geometry* geo, const lb
     h->ddesc = (Desc*)(h->base + h->L.off_desc);
     h->dtiles = (Tile*)(h->base + h->L.off_tiles);
     h->ntiles = (int)h->L.tiles.size();
+    h->dghosts = (GhostRef*)(h->base + h->L.off_ghosts);
+    h->nghosts = (int)h->L.ghosts.size();
     h->step = h->hdesc.step;
     // the host copies of flags and links are no longer needed
     std::vector<uint8_t>().swap(h->L.flag);
@@ -168,6 +172,8 @@ extern "C" int lbm_step(lbm_handle* h, int64_t nsteps) {
         if (h->timing) HIPRET(hipEventRecord(e1, h->stream));
         HIPRET(launch_sweep(storage, MODE_STEP, h->L.tx, par, h->ddesc, h->dtiles, h->ntiles, diag, ro, in,
                             h->stream));
+        if (h->nghosts)
+            HIPRET(launch_ghosts(storage, h->ddesc, h->dghosts, h->nghosts, h->stream));
         if (h->timing) HIPRET(hipEventRecord(e2, h->stream));
     }
     h->step += nsteps;

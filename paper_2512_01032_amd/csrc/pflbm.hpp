@@ -63,6 +63,9 @@ struct alignas(256) Desc {
     const uint32_t* link;
     double* partials;              // [ntiles][NPART]
     unsigned int* counter;         // tiles finished in the current sweep
+    void* gbuf;                    // [3][face entries] u of each ghost's owner (compute type)
+    int64_t gface_base[6];         // first entry of each face plane in gbuf
+    int64_t gface_count;           // entries per velocity component
     // time
     int64_t step;                  // advanced on the device by the last tile of a sweep
     int64_t t0;                    // step counter value at physical time 0
@@ -83,11 +86,22 @@ struct alignas(256) Desc {
     double href, gref;             // shift references (0 for plain storage)
     double scale_h, scale_g;       // storage scales (1 except FP16)
     double u_max;
+    // derived constants in the compute precision (host-computed, read as
+    // scalars by the kernels): index names in enum ParamIndex
+    float pf[32];
+    double pd[32];
     // outputs of the last diagnostic reduction
     double diag[NPART];
     int64_t diag_step;
     int32_t unstable;              // sticky: NaN or |u| > u_max seen
     int32_t pad1;
+};
+
+enum ParamIndex {
+    PI_RHO_G = 0, PI_RDIF, PI_MU3, PI_MULAP, PI_TAU_G, PI_TAU_L, PI_THETA0, PI_MC_K, PI_MC_INVD,
+    PI_MC_PHI_M, PI_MC_PHI_m, PI_EPS, PI_MIX_PHI, PI_MIX_INVW, PI_SLIP_LO, PI_SLIP_HI, PI_CLAMP_A,
+    PI_HREF, PI_GREF, PI_SH, PI_SG, PI_INV_SH, PI_INV_SG, PI_ITAU_H, PI_FX, PI_FY, PI_FZ,
+    PI_K2W, PI_PREF_DEV, PI_COUNT
 };
 
 // diagnostic partial slots
@@ -97,6 +111,20 @@ enum { P_PHI = 0, P_MX, P_MY, P_MZ, P_UMAX, P_NAN, P_PLIQ, P_NLIQ, P_PGAS, P_NGA
 constexpr int MODE_STEP = 0;   // stream + collide, AA in place
 constexpr int MODE_READ = 1;   // macroscopic fields / populations to output buffers
 constexpr int MODE_INIT = 2;   // equilibria from (phi, u, P) into even-parity slots
+
+struct GhostRef {              // one pressure ghost: lattice and node
+    int32_t lat;
+    int32_t node;
+};
+
+// entry of a ghost node (x, y, z) on face f in the face buffer
+__host__ __device__ inline int64_t ghost_slot(const int64_t* base, int f, int x, int y, int z,
+                                              int nx, int ny) {
+    const int ax = f >> 1;
+    if (ax == 0) return base[f] + y + (int64_t)ny * z;
+    if (ax == 1) return base[f] + x + (int64_t)nx * z;
+    return base[f] + x + (int64_t)nx * y;
+}
 
 struct ReadOut {               // device buffers of MODE_READ (NULL: skip)
     double* phi;
@@ -119,5 +147,9 @@ hipError_t launch_sweep(int storage, int mode, int tx, int parity, Desc* d, cons
                         int ntiles, int diag, ReadOut ro, InitIn in, hipStream_t s);
 hipError_t launch_restore(int storage, int parity, const Desc* d, const Tile* tiles, int ntiles,
                           const double* pops, hipStream_t s);
+// after a sweep: equilibrium populations of every listed pressure ghost for
+// the next step (the step counter the sweep advanced), from its owner's u
+hipError_t launch_ghosts(int storage, const Desc* d, const GhostRef* ghosts, int nghosts,
+                         hipStream_t s);
 
 }  // namespace pflbm
