@@ -55,6 +55,88 @@ def measured_traffic(storage):
     return rec.get("bytes_per_sweep", {}).get(storage)
 
 
+def copy_calibration(mib, torch):
+    """A plain streaming kernel of known traffic (elementwise negation: reads
+    and writes mib MiB), run a few times; its counter readings calibrate
+    FETCH_SIZE / WRITE_SIZE against bytes actually moved."""
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        torch.neg(a, out=b)
+    torch.cuda.synchronize()
+    print("[bench] copy calibration: %d MiB x 3" % mib, file=sys.stderr, flush=True)
+    del a, b
+
+
+_TYPES = {"float": "f32", "f": "f32", "double": "f64", "d": "f64", "_Float16": "f16", "DF16_": "f16"}
+_STORAGE = {("f32", "f32", "f32"): "fp32_shift", ("f32", "f32", "f16"): "fp16_shift_g",
+            ("f32", "f16", "f16"): "fp16_shift_all", ("f64", "f64", "f64"): "fp64"}
+
+
+def _sweep_storage(name):
+    """Storage mode of a MODE_STEP sweep dispatch from its kernel name
+    (demangled or mangled), else None."""
+    import re
+    m = re.search(r"sweep_kernel<(\w+), (\w+), (\w+), 0,", name)
+    if not m:
+        m = re.search(r"sweep_kernelI(f|d)(f|d|DF16_)(f|d|DF16_)Li0E", name)
+    if not m:
+        return None
+    return _STORAGE.get(tuple(_TYPES[t] for t in m.groups()))
+
+
+def _counter_rows(path, counter):
+    import csv
+    out = []
+    for r in csv.DictReader(open(path)):
+        if r.get("Counter_Name") == counter:
+            out.append((r["Kernel_Name"], float(r["Counter_Value"]), int(r["Grid_Size"])))
+    return out
+
+
+def fold_traffic(fetch_csv, write_csv, mib):
+    """Per-launch HBM bytes of the sweep from FETCH_SIZE and WRITE_SIZE (KiB
+    per dispatch), each scaled by the factor that maps the same counter on the
+    calibration copy to the bytes it moved."""
+    rec = {"kernel_hash": kernel_hash(), "bytes_per_sweep": {}, "fetch_bytes": {},
+           "write_bytes": {}, "calibration": {}, "copy_mib": mib}
+    for key, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
+        rows = _counter_rows(path, counter)
+        cal = [(v, g) for n, v, g in rows if "neg" in n]
+        if not cal:
+            raise SystemExit("no calibration copy dispatch in %s" % path)
+        # the copy kernel's grid covers n/4 float4 or n floats; its traffic is
+        # the tensor size, taken from the largest dispatch (the 1 GiB copies)
+        kib = max(v for v, g in cal)
+        rec["calibration"][key] = {"counter_kib": kib}
+        per = {}
+        for n, v, g in rows:
+            s = _sweep_storage(n)
+            if s is not None:
+                per.setdefault(s, []).append(v)
+        rec["calibration"][key]["per_storage_dispatches"] = {s: len(v) for s, v in per.items()}
+        for s, vals in per.items():
+            rec[key + "_bytes"][s] = sum(vals) / len(vals) * 1024.0
+    return _finish_fold(rec)
+
+
+def _finish_fold(rec):
+    mib = rec["copy_mib"]
+    nbytes = mib * (1 << 20)
+    ff = nbytes / (rec["calibration"]["fetch"]["counter_kib"] * 1024.0)
+    fw = nbytes / (rec["calibration"]["write"]["counter_kib"] * 1024.0)
+    rec["calibration"]["fetch"]["factor"] = ff
+    rec["calibration"]["write"]["factor"] = fw
+    for s in rec["fetch_bytes"]:
+        if s in rec["write_bytes"]:
+            rec["bytes_per_sweep"][s] = rec["fetch_bytes"][s] * ff + rec["write_bytes"][s] * fw
+    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(rec, f, indent=1, sort_keys=True)
+    print(json.dumps(rec["bytes_per_sweep"]))
+
+
 def run_gpu(wl, storage, steps, warmup, torch):
     from paper_2512_01032_amd import lbm
     stream = torch.cuda.current_stream()
@@ -88,7 +170,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--modes", default="fp32_shift,fp16_shift_g,fp32,fp64")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="first run a plain device copy of this many MiB (the calibration "
+                         "kernel for the HBM byte counters)")
+    ap.add_argument("--fold-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="fold two rocprofv3 --pmc counter_collection.csv files (FETCH_SIZE, "
+                         "WRITE_SIZE) into the per-launch traffic record and exit")
     args = ap.parse_args()
+    if args.fold_traffic:
+        fold_traffic(*args.fold_traffic, mib=args.copy_mib or 1024)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the lattice of this workload fits one MI355X and "
               "the multi-GPU (z-slab halo exchange) path is not built; use --gpus 1",
@@ -103,6 +194,8 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
 
+    if args.copy_mib > 0:
+        copy_calibration(args.copy_mib, torch)
     wl = inputs.constricted_duct()
     modes = args.modes.split(",")
     results = {}
