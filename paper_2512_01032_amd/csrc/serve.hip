@@ -1,24 +1,595 @@
-// serve.hip -- continuous-batching server (placeholder until the batched
-// scheduler lands): every entry point reports LBM_E_STATE.
+// serve.hip -- continuous batching of independent lattices on one GPU.
+//
+// A worker thread owns the GPU side.  Requests wait in a FIFO queue; the head
+// is admitted when a descriptor slot is free and its footprint fits in a
+// free block of the server's HBM arena.  Every admitted lattice starts at
+// step 0.  Work proceeds in scheduling intervals of an even number of steps:
+// each step is one phi launch over the concatenated tile tables of all
+// resident lattices, one sweep launch per tile width and one ghost launch.
+// Because intervals are even and lattices join only at interval boundaries,
+// all resident lattices share the AA parity of every step; a lattice whose
+// step count is reached stops on the device (its tiles return at once) and
+// is read back and evicted at the next boundary.  Tiles never mix lattices
+// and every reduction is per lattice, so a lattice's result does not depend
+// on what it was batched with.
+#include <hip/hip_runtime.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <string>
+#include <unordered_map>
+#include <unordered_set>
+#include <vector>
+
 #include "../../include/lbm.h"
 #include "lattice_host.hpp"
+#include "pflbm.hpp"
 
 using namespace pflbm;
 
-extern "C" int lbm_server_create(const lbm_server_cfg*, lbm_server** out) {
-    if (out) *out = nullptr;
-    set_error("serving is not available in this build");
-    return LBM_E_STATE;
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t round_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
+
+// First-fit allocator over [0, size) with coalescing of freed blocks.
+class ArenaAllocator {
+public:
+    void reset(size_t size) { free_.clear(); if (size) free_[0] = size; }
+    bool alloc(size_t n, size_t* off) {
+        n = round_up(n);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < n) continue;
+            *off = it->first;
+            const size_t rest = it->second - n, at = it->first + n;
+            free_.erase(it);
+            if (rest) free_[at] = rest;
+            return true;
+        }
+        return false;
+    }
+    void release(size_t off, size_t n) {
+        n = round_up(n);
+        auto next = free_.lower_bound(off);
+        if (next != free_.end() && off + n == next->first) { n += next->second; next = free_.erase(next); }
+        if (next != free_.begin()) {
+            auto prev = std::prev(next);
+            if (prev->first + prev->second == off) { prev->second += n; return; }
+        }
+        free_[off] = n;
+    }
+    size_t largest() const {
+        size_t m = 0;
+        for (auto& kv : free_) m = std::max(m, kv.second);
+        return m;
+    }
+private:
+    std::map<size_t, size_t> free_;
+};
+
+struct Job {
+    uint64_t ticket = 0;
+    lbm_params p;
+    lbm_geometry geo;
+    std::vector<uint8_t> solid;
+    std::vector<double> phi0, u0, P0;
+    int64_t nsteps = 0;
+    double arrival_s = 0.0;
+    double t_submit = 0.0, t_admit = 0.0, t_finish = 0.0;
+    // placement
+    bool laid_out = false;
+    LatticeLayout L;
+    size_t off = 0, bytes = 0;
+    int slot = -1;
+    Desc hdesc;
+    int64_t step = 0;
+    // result
+    int status = LBM_OK;
+    double *phi = nullptr, *P = nullptr, *u = nullptr;
+    lbm_diag diag;
+    ~Job() { free(phi); free(P); free(u); }
+};
+
+}  // namespace
+
+struct lbm_server {
+    lbm_server_cfg cfg;
+    int interval = 32;
+    hipStream_t stream = nullptr;
+    char* arena = nullptr;
+    size_t arena_bytes = 0;
+    ArenaAllocator alloc;
+    Desc* dtable = nullptr;
+    Desc* hmirror = nullptr;     // pinned copy of the table after each interval
+    std::vector<int> free_slots;
+    hipEvent_t ev = nullptr;
+    // batched work tables
+    Tile* dtiles = nullptr;
+    size_t tiles_cap = 0;
+    GhostRef* dghosts = nullptr;
+    size_t ghosts_cap = 0;
+    struct Group { int tx, off, n; };
+    std::vector<Group> groups;
+    int ntiles = 0, nghosts = 0, table_slots = 0;
+    bool dirty = true;
+    hipGraphExec_t gexec = nullptr;
+    // jobs
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<std::unique_ptr<Job>> queue;
+    std::vector<std::unique_ptr<Job>> active;                  // worker thread only
+    std::unordered_map<uint64_t, std::unique_ptr<Job>> done;
+    std::unordered_set<uint64_t> in_flight;                     // queued or resident
+    uint64_t next_ticket = 1;
+    int64_t outstanding = 0;
+    bool stop = false;
+    int fatal = LBM_OK;
+    std::string fatal_msg;
+    std::thread worker;
+    std::chrono::steady_clock::time_point t0;
+
+    double now() const {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+};
+
+namespace {
+
+int device_error(const char* what, hipError_t e) {
+    set_error("%s: %s", what, hipGetErrorString(e));
+    return LBM_E_DEVICE;
 }
-extern "C" int lbm_submit(lbm_server*, const lbm_request*, uint64_t*) {
-    set_error("serving is not available in this build");
-    return LBM_E_STATE;
+
+#define SRV_CHK(expr)                                          \
+    do {                                                       \
+        hipError_t e_ = (expr);                                \
+        if (e_ != hipSuccess) return device_error(#expr, e_);  \
+    } while (0)
+
+void finish_job(lbm_server* s, std::unique_ptr<Job> job) {
+    job->t_finish = s->now();
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->outstanding -= 1;
+    s->in_flight.erase(job->ticket);
+    s->done[job->ticket] = std::move(job);
+    s->cv_done.notify_all();
 }
-extern "C" int lbm_poll(lbm_server*, uint64_t, lbm_result*) {
-    set_error("serving is not available in this build");
-    return LBM_E_STATE;
+
+// Place the head of the queue, if it fits.  Returns 1 if a lattice was
+// admitted, 0 if the head must wait, <0 on a device error.
+int admit_one(lbm_server* s) {
+    std::unique_ptr<Job> job;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->queue.empty()) return 0;
+        job = std::move(s->queue.front());
+        s->queue.pop_front();
+    }
+    auto requeue = [&]() {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->queue.push_front(std::move(job));
+    };
+    if (!job->laid_out) {
+        const int rc = build_layout(&job->p, &job->geo, 0, &job->L);
+        if (rc != LBM_OK) { job->status = rc; finish_job(s, std::move(job)); return 1; }
+        job->laid_out = true;
+        job->bytes = job->L.total;
+    }
+    if (s->free_slots.empty() || !s->alloc.alloc(job->bytes, &job->off)) {
+        if (s->active.empty()) {
+            // nothing will be freed: the request can never be placed
+            set_error("request of %zu bytes does not fit the arena", job->bytes);
+            job->status = LBM_E_NOMEM;
+            finish_job(s, std::move(job));
+            return 1;
+        }
+        requeue();
+        return 0;
+    }
+    job->slot = s->free_slots.back();
+    s->free_slots.pop_back();
+    lbm_init init;
+    memset(&init, 0, sizeof(init));
+    init.kind = LBM_INIT_FIELDS;
+    init.phi = job->phi0.data();
+    init.u = job->u0.empty() ? nullptr : job->u0.data();
+    init.P = job->P0.empty() ? nullptr : job->P0.data();
+    int rc = upload_and_init(&job->p, &job->geo, &init, job->L, s->arena + job->off,
+                             &job->hdesc, s->stream);
+    if (rc == LBM_OK) {
+        job->hdesc.stop_step = job->nsteps;
+        hipError_t e = hipMemcpyAsync(s->dtable + job->slot, &job->hdesc, sizeof(Desc),
+                                      hipMemcpyHostToDevice, s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) rc = device_error("descriptor upload", e);
+    }
+    if (rc != LBM_OK) {
+        job->status = rc;
+        finish_job(s, std::move(job));
+        return rc;
+    }
+    // host copies no longer needed once the lattice is on the device
+    std::vector<double>().swap(job->phi0);
+    std::vector<double>().swap(job->u0);
+    std::vector<double>().swap(job->P0);
+    std::vector<uint8_t>().swap(job->solid);
+    std::vector<uint8_t>().swap(job->L.flag);
+    std::vector<uint32_t>().swap(job->L.link);
+    job->geo.solid = nullptr;
+    job->t_admit = s->now();
+    job->step = 0;
+    s->active.push_back(std::move(job));
+    s->dirty = true;
+    return 1;
 }
-extern "C" int lbm_server_drain(lbm_server*) { return LBM_E_STATE; }
-extern "C" double lbm_server_clock(const lbm_server*) { return 0.0; }
-extern "C" void lbm_result_free(lbm_result*) {}
-extern "C" int lbm_server_destroy(lbm_server*) { return LBM_OK; }
+
+// Concatenated tile tables of all resident lattices, grouped by tile width.
+int rebuild_tables(lbm_server* s) {
+    std::vector<Tile> tiles;
+    std::vector<GhostRef> ghosts;
+    s->groups.clear();
+    s->table_slots = 0;
+    for (int tx : {64, 32, 16}) {
+        const int off = (int)tiles.size();
+        for (auto& j : s->active) {
+            if (j->L.tx != tx) continue;
+            for (Tile t : j->L.tiles) { t.lat = j->slot; tiles.push_back(t); }
+        }
+        if ((int)tiles.size() > off) s->groups.push_back({tx, off, (int)tiles.size() - off});
+    }
+    for (auto& j : s->active) {
+        for (GhostRef g : j->L.ghosts) { g.lat = j->slot; ghosts.push_back(g); }
+        s->table_slots = std::max(s->table_slots, j->slot + 1);
+    }
+    if (tiles.size() > s->tiles_cap) {
+        if (s->dtiles) SRV_CHK(hipFree(s->dtiles));
+        s->dtiles = nullptr;
+        s->tiles_cap = std::max(tiles.size(), 2 * s->tiles_cap);
+        SRV_CHK(hipMalloc(&s->dtiles, s->tiles_cap * sizeof(Tile)));
+    }
+    if (ghosts.size() > s->ghosts_cap) {
+        if (s->dghosts) SRV_CHK(hipFree(s->dghosts));
+        s->dghosts = nullptr;
+        s->ghosts_cap = std::max(ghosts.size(), 2 * s->ghosts_cap);
+        SRV_CHK(hipMalloc(&s->dghosts, s->ghosts_cap * sizeof(GhostRef)));
+    }
+    if (!tiles.empty())
+        SRV_CHK(hipMemcpyAsync(s->dtiles, tiles.data(), tiles.size() * sizeof(Tile),
+                               hipMemcpyHostToDevice, s->stream));
+    if (!ghosts.empty())
+        SRV_CHK(hipMemcpyAsync(s->dghosts, ghosts.data(), ghosts.size() * sizeof(GhostRef),
+                               hipMemcpyHostToDevice, s->stream));
+    SRV_CHK(hipStreamSynchronize(s->stream));
+    s->ntiles = (int)tiles.size();
+    s->nghosts = (int)ghosts.size();
+    if (s->gexec) { SRV_CHK(hipGraphExecDestroy(s->gexec)); s->gexec = nullptr; }
+    s->dirty = false;
+    return LBM_OK;
+}
+
+// The launches of one interval (every step starts at the parity of its index).
+hipError_t enqueue_steps(lbm_server* s) {
+    const int storage = s->cfg.storage;
+    const ReadOut ro = {nullptr, nullptr, nullptr, nullptr};
+    const InitIn in = {nullptr, nullptr};
+    for (int k = 0; k < s->interval; ++k) {
+        const int par = k & 1;
+        hipError_t e = launch_phi(storage, par, s->dtable, s->dtiles, s->ntiles, s->stream, 0);
+        for (const auto& g : s->groups)
+            if (e == hipSuccess)
+                e = launch_sweep(storage, MODE_STEP, g.tx, par, s->dtable, s->dtiles + g.off, g.n, 0,
+                                 ro, in, s->stream);
+        if (e == hipSuccess && s->nghosts)
+            e = launch_ghosts(storage, s->dtable, s->dghosts, s->nghosts, s->stream);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+int run_interval(lbm_server* s) {
+    if (s->cfg.use_graph) {
+        if (!s->gexec) {
+            hipGraph_t g = nullptr;
+            SRV_CHK(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+            const hipError_t e = enqueue_steps(s);
+            const hipError_t e2 = hipStreamEndCapture(s->stream, &g);
+            if (e != hipSuccess) return device_error("capture", e);
+            if (e2 != hipSuccess) return device_error("hipStreamEndCapture", e2);
+            const hipError_t e3 = hipGraphInstantiate(&s->gexec, g, nullptr, nullptr, 0);
+            hipGraphDestroy(g);
+            if (e3 != hipSuccess) return device_error("hipGraphInstantiate", e3);
+        }
+        SRV_CHK(hipGraphLaunch(s->gexec, s->stream));
+    } else {
+        SRV_CHK(enqueue_steps(s));
+    }
+    SRV_CHK(hipMemcpyAsync(s->hmirror, s->dtable, (size_t)s->table_slots * sizeof(Desc),
+                           hipMemcpyDeviceToHost, s->stream));
+    SRV_CHK(hipEventRecord(s->ev, s->stream));
+    SRV_CHK(hipEventSynchronize(s->ev));
+    return LBM_OK;
+}
+
+int finalize(lbm_server* s, std::unique_ptr<Job> job) {
+    const int64_t N = job->L.N;
+    job->phi = (double*)malloc(N * sizeof(double));
+    job->P = (double*)malloc(N * sizeof(double));
+    job->u = (double*)malloc(3 * N * sizeof(double));
+    if (!job->phi || !job->P || !job->u) {
+        set_error("host allocation of a result failed");
+        job->status = LBM_E_NOMEM;
+    } else {
+        Desc* dd = s->dtable + job->slot;
+        const Tile* dt = (const Tile*)(s->arena + job->off + job->L.off_tiles);
+        int rc = read_lattice(s->cfg.storage, job->hdesc, (int)(job->nsteps & 1), dd, dt,
+                              (int)job->L.tiles.size(), LBM_PHI | LBM_P | LBM_U, job->phi, job->P,
+                              job->u, nullptr, s->stream);
+        double v[NPART];
+        if (rc == LBM_OK) {
+            const hipError_t e = hipMemcpy(v, dd->diag, sizeof(v), hipMemcpyDeviceToHost);
+            if (e != hipSuccess) rc = device_error("diagnostics copy", e);
+        }
+        if (rc != LBM_OK) {
+            job->status = rc;
+            finish_job(s, std::move(job));
+            return rc;
+        }
+        lbm_diag& d = job->diag;
+        d.step = job->nsteps;
+        d.phi_sum = v[P_PHI];
+        d.mom[0] = v[P_MX]; d.mom[1] = v[P_MY]; d.mom[2] = v[P_MZ];
+        d.u_max = v[P_UMAX];
+        d.n_nan = (int64_t)v[P_NAN];
+        d.n_liq = (int64_t)v[P_NLIQ];
+        d.n_gas = (int64_t)v[P_NGAS];
+        d.P_liq_mean = d.n_liq ? v[P_PLIQ] / (double)d.n_liq : 0.0;
+        d.P_gas_mean = d.n_gas ? v[P_PGAS] / (double)d.n_gas : 0.0;
+        job->status = d.n_nan ? LBM_E_UNSTABLE : LBM_OK;
+    }
+    s->alloc.release(job->off, job->bytes);
+    s->free_slots.push_back(job->slot);
+    s->dirty = true;
+    finish_job(s, std::move(job));
+    return LBM_OK;
+}
+
+// One scheduling point: evict finished lattices, admit from the queue.
+int schedule(lbm_server* s) {
+    for (size_t k = 0; k < s->active.size();) {
+        Job* j = s->active[k].get();
+        if (j->step >= j->nsteps) {
+            std::unique_ptr<Job> job = std::move(s->active[k]);
+            s->active.erase(s->active.begin() + k);
+            const int rc = finalize(s, std::move(job));
+            if (rc != LBM_OK) return rc;
+        } else {
+            ++k;
+        }
+    }
+    for (;;) {
+        const int rc = admit_one(s);
+        if (rc < 0) return rc;
+        if (rc == 0) break;
+    }
+    return LBM_OK;
+}
+
+void fail_all(lbm_server* s, int code) {
+    const char* msg = lbm_last_error();
+    std::vector<std::unique_ptr<Job>> jobs;
+    for (auto& j : s->active) jobs.push_back(std::move(j));
+    s->active.clear();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        for (auto& j : s->queue) jobs.push_back(std::move(j));
+        s->queue.clear();
+        s->fatal = code;
+        s->fatal_msg = msg ? msg : "";
+    }
+    for (auto& j : jobs) { j->status = code; finish_job(s, std::move(j)); }
+}
+
+void worker_main(lbm_server* s) {
+    if (hipSetDevice(s->cfg.device) != hipSuccess) { fail_all(s, LBM_E_DEVICE); return; }
+    for (;;) {
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty() || !s->active.empty(); });
+            if (s->stop) break;
+        }
+        int rc = schedule(s);
+        if (rc == LBM_OK && !s->active.empty()) {
+            if (s->dirty) rc = rebuild_tables(s);
+            if (rc == LBM_OK) rc = run_interval(s);
+            if (rc == LBM_OK) {
+                for (auto& j : s->active) {
+                    j->step = std::min(j->step + s->interval, j->nsteps);
+                    if (s->hmirror[j->slot].step != j->step) {
+                        set_error("lattice in slot %d is at step %lld, expected %lld", j->slot,
+                                  (long long)s->hmirror[j->slot].step, (long long)j->step);
+                        rc = LBM_E_STATE;
+                        break;
+                    }
+                }
+            }
+        }
+        if (rc != LBM_OK) { fail_all(s, rc); return; }
+    }
+}
+
+}  // namespace
+
+extern "C" int lbm_server_create(const lbm_server_cfg* cfg, lbm_server** out) {
+    if (!out || !cfg) { set_error("NULL argument"); return LBM_E_INVAL; }
+    *out = nullptr;
+    if (cfg->max_slots < 0 || cfg->max_slots > 256) { set_error("max_slots must be in [0, 256]"); return LBM_E_INVAL; }
+    if (cfg->storage < LBM_FP64 || cfg->storage > LBM_FP16_SHIFT_ALL) {
+        set_error("unknown storage mode %d", cfg->storage);
+        return LBM_E_INVAL;
+    }
+    if (cfg->ticks_per_sync < 0) { set_error("ticks_per_sync < 0"); return LBM_E_INVAL; }
+    std::unique_ptr<lbm_server> s(new (std::nothrow) lbm_server());
+    if (!s) { set_error("host allocation failed"); return LBM_E_NOMEM; }
+    s->cfg = *cfg;
+    if (s->cfg.max_slots == 0) s->cfg.max_slots = 256;
+    const int k = cfg->ticks_per_sync ? cfg->ticks_per_sync : 32;
+    s->interval = (k + 1) / 2 * 2;
+    auto cleanup = [&](int rc) {
+        if (s->ev) hipEventDestroy(s->ev);
+        if (s->hmirror) hipHostFree(s->hmirror);
+        if (s->dtable) hipFree(s->dtable);
+        if (s->arena) hipFree(s->arena);
+        if (s->stream) hipStreamDestroy(s->stream);
+        return rc;
+    };
+    hipError_t e = hipSetDevice(cfg->device);
+    if (e != hipSuccess) return cleanup(device_error("hipSetDevice", e));
+    size_t budget = cfg->hbm_budget;
+    if (budget == 0) {
+        size_t fr = 0, tot = 0;
+        e = hipMemGetInfo(&fr, &tot);
+        if (e != hipSuccess) return cleanup(device_error("hipMemGetInfo", e));
+        budget = fr / 10 * 8;
+    }
+    budget = budget / kAlign * kAlign;
+    if (budget == 0) { set_error("HBM budget is zero"); return LBM_E_INVAL; }
+    e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMalloc(&s->arena, budget);
+    if (e == hipSuccess) e = hipMalloc(&s->dtable, (size_t)s->cfg.max_slots * sizeof(Desc));
+    if (e == hipSuccess) e = hipHostMalloc((void**)&s->hmirror, (size_t)s->cfg.max_slots * sizeof(Desc),
+                                           hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        const int rc = e == hipErrorOutOfMemory ? LBM_E_NOMEM : LBM_E_DEVICE;
+        set_error("server set-up: %s", hipGetErrorString(e));
+        return cleanup(rc);
+    }
+    s->arena_bytes = budget;
+    s->alloc.reset(budget);
+    for (int i = s->cfg.max_slots - 1; i >= 0; --i) s->free_slots.push_back(i);
+    s->t0 = std::chrono::steady_clock::now();
+    lbm_server* raw = s.release();
+    raw->worker = std::thread(worker_main, raw);
+    *out = raw;
+    return LBM_OK;
+}
+
+extern "C" int lbm_submit(lbm_server* s, const lbm_request* req, uint64_t* ticket) {
+    if (!s || !req || !ticket) { set_error("NULL argument"); return LBM_E_INVAL; }
+    const double t = s->now();
+    std::unique_ptr<Job> job(new (std::nothrow) Job());
+    if (!job) { set_error("host allocation failed"); return LBM_E_NOMEM; }
+    job->p = req->params;
+    job->p.storage = s->cfg.storage;
+    job->p.diag_every = 0;
+    job->geo = req->geometry;
+    if (req->init.kind != LBM_INIT_FIELDS || !req->init.phi) {
+        set_error("a request starts from fields (LBM_INIT_FIELDS with phi)");
+        return LBM_E_INVAL;
+    }
+    if (req->nsteps < 1) { set_error("nsteps must be >= 1"); return LBM_E_INVAL; }
+    int rc = validate_params(&job->p, &job->geo);
+    if (rc != LBM_OK) return rc;
+    const size_t need = footprint_bytes(&job->p);
+    if (need > s->arena_bytes) {
+        set_error("footprint %zu bytes exceeds the server budget %zu", need, s->arena_bytes);
+        return LBM_E_INVAL;
+    }
+    const int64_t N = (int64_t)job->p.nx * job->p.ny * job->p.nz;
+    try {
+        if (req->geometry.solid) job->solid.assign(req->geometry.solid, req->geometry.solid + N);
+        job->phi0.assign(req->init.phi, req->init.phi + N);
+        if (req->init.u) job->u0.assign(req->init.u, req->init.u + 3 * N);
+        if (req->init.P) job->P0.assign(req->init.P, req->init.P + N);
+    } catch (...) {
+        set_error("host allocation failed");
+        return LBM_E_NOMEM;
+    }
+    job->geo.solid = job->solid.empty() ? nullptr : job->solid.data();
+    job->nsteps = req->nsteps;
+    job->arrival_s = req->arrival_s;
+    job->t_submit = t;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->fatal != LBM_OK) { set_error("server stopped: %s", s->fatal_msg.c_str()); return s->fatal; }
+    job->ticket = s->next_ticket++;
+    *ticket = job->ticket;
+    s->outstanding += 1;
+    s->in_flight.insert(job->ticket);
+    s->queue.push_back(std::move(job));
+    s->cv_work.notify_one();
+    return LBM_OK;
+}
+
+extern "C" int lbm_poll(lbm_server* s, uint64_t ticket, lbm_result* res) {
+    if (!s || !res) { set_error("NULL argument"); return LBM_E_INVAL; }
+    std::unique_ptr<Job> job;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        auto it = s->done.find(ticket);
+        if (it == s->done.end()) {
+            if (s->in_flight.count(ticket)) return LBM_PENDING;
+            set_error("ticket %llu is unknown or was already returned", (unsigned long long)ticket);
+            return LBM_E_INVAL;
+        }
+        job = std::move(it->second);
+        s->done.erase(it);
+    }
+    memset(res, 0, sizeof(*res));
+    res->status = job->status;
+    res->nx = job->p.nx; res->ny = job->p.ny; res->nz = job->p.nz;
+    res->phi = job->phi; res->P = job->P; res->u = job->u;
+    job->phi = job->P = job->u = nullptr;
+    res->diag = job->diag;
+    res->t_submit_s = job->t_submit;
+    res->t_admit_s = job->t_admit;
+    res->t_finish_s = job->t_finish;
+    res->steps = job->status == LBM_OK ? job->nsteps : job->step;
+    return LBM_OK;
+}
+
+extern "C" int lbm_server_drain(lbm_server* s) {
+    if (!s) { set_error("NULL argument"); return LBM_E_INVAL; }
+    std::unique_lock<std::mutex> lk(s->mu);
+    s->cv_done.wait(lk, [&] { return s->outstanding == 0; });
+    if (s->fatal != LBM_OK) { set_error("server stopped: %s", s->fatal_msg.c_str()); return s->fatal; }
+    return LBM_OK;
+}
+
+extern "C" double lbm_server_clock(const lbm_server* s) { return s ? s->now() : 0.0; }
+
+extern "C" void lbm_result_free(lbm_result* res) {
+    if (!res) return;
+    free(res->phi); free(res->P); free(res->u);
+    res->phi = res->P = res->u = nullptr;
+}
+
+extern "C" int lbm_server_destroy(lbm_server* s) {
+    if (!s) return LBM_OK;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        s->cv_work.notify_all();
+    }
+    if (s->worker.joinable()) s->worker.join();
+    hipSetDevice(s->cfg.device);
+    if (s->stream) hipStreamSynchronize(s->stream);
+    if (s->gexec) hipGraphExecDestroy(s->gexec);
+    if (s->dtiles) hipFree(s->dtiles);
+    if (s->dghosts) hipFree(s->dghosts);
+    if (s->ev) hipEventDestroy(s->ev);
+    if (s->hmirror) hipHostFree(s->hmirror);
+    if (s->dtable) hipFree(s->dtable);
+    if (s->arena) hipFree(s->arena);
+    if (s->stream) hipStreamDestroy(s->stream);
+    delete s;
+    return LBM_OK;
+}

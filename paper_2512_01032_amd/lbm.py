@@ -288,3 +288,77 @@ class Lattice:
 def footprint(wl, storage=None):
     p = params_from_workload(wl, storage)
     return int(lbm_footprint(ctypes.byref(p)))
+
+
+class Server:
+    """Continuous-batching server through the C ABI (lbm_server_*)."""
+
+    def __init__(self, storage="fp32_shift", hbm_budget=0, max_slots=0, use_graph=True,
+                 ticks_per_sync=32, device=0):
+        cfg = lbm_server_cfg()
+        cfg.hbm_budget = int(hbm_budget)
+        cfg.max_slots = int(max_slots)
+        cfg.storage = STORAGE[storage]
+        cfg.device = int(device)
+        cfg.use_graph = int(bool(use_graph))
+        cfg.ticks_per_sync = int(ticks_per_sync)
+        h = ctypes.c_void_p()
+        check(lbm_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lbm_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def submit(self, wl, nsteps, arrival_s=0.0):
+        """Queue a workload for nsteps steps; the arrays are copied during the call."""
+        req = lbm_request()
+        req.params = params_from_workload(wl)
+        solid = _arr(wl.solid, np.uint8)
+        phi0, u0, P0 = _arr(wl.phi0), _arr(wl.u0), _arr(wl.P0)
+        req.geometry.solid = None if solid is None else solid.ctypes.data
+        for k in range(16):
+            req.geometry.theta_deg[k] = wl.theta_deg[k]
+        req.init.kind = LBM_INIT_FIELDS
+        req.init.phi = phi0.ctypes.data
+        req.init.u = None if u0 is None else u0.ctypes.data
+        req.init.P = None if P0 is None else P0.ctypes.data
+        req.nsteps = int(nsteps)
+        req.arrival_s = float(arrival_s)
+        t = ctypes.c_uint64()
+        check(lbm_submit(self.h, ctypes.byref(req), ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket):
+        """None while pending, else a dict with the request's status, fields,
+        diagnostics and server-clock timestamps."""
+        r = lbm_result()
+        rc = check(lbm_poll(self.h, ctypes.c_uint64(ticket), ctypes.byref(r)))
+        if rc == LBM_PENDING:
+            return None
+        try:
+            shape = (r.nz, r.ny, r.nx)
+            n = r.nx * r.ny * r.nz
+            out = {"status": r.status, "steps": r.steps, "t_submit": r.t_submit_s,
+                   "t_admit": r.t_admit_s, "t_finish": r.t_finish_s}
+            if r.status == LBM_OK:
+                out["phi"] = np.ctypeslib.as_array(r.phi, (n,)).reshape(shape).copy()
+                out["P"] = np.ctypeslib.as_array(r.P, (n,)).reshape(shape).copy()
+                out["u"] = np.ctypeslib.as_array(r.u, (3 * n,)).reshape((3,) + shape).copy()
+                d = r.diag
+                out["diag"] = {"step": d.step, "phi_sum": d.phi_sum, "mom": tuple(d.mom),
+                               "u_max": d.u_max, "P_liq_mean": d.P_liq_mean,
+                               "P_gas_mean": d.P_gas_mean, "n_nan": d.n_nan}
+            return out
+        finally:
+            lbm_result_free(ctypes.byref(r))
+
+    def drain(self):
+        check(lbm_server_drain(self.h))
+
+    def clock(self):
+        return lbm_server_clock(self.h)

@@ -1,0 +1,132 @@
+"""Continuous-batching server through the C ABI.
+
+The server advances every resident lattice with one launch per kernel over
+the concatenation of their tile tables.  A request's result must not depend
+on what it is batched with: each result in a mix is compared with the same
+request run alone through lbm_create/lbm_step, bitwise (tolerance 0), with
+requests of both kinds, several tile widths, odd and even step counts that
+end inside a scheduling interval, and admission held back by the HBM budget
+and by the slot count.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+import pytest
+
+from tests.gpu_util import require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _lbm():
+    require_gpu()
+    from paper_2512_01032_amd import lbm
+    return lbm
+
+
+def _mix():
+    from paper_2512_01032_amd import inputs
+    return [
+        inputs.droplet_on_wall(32, 50.0, 37),      # tile width 32
+        inputs.channel_filling(32, 120.0, 40),     # tile width 64, pressure faces
+        inputs.droplet_on_wall(48, 135.0, 64),     # tile width 16
+        inputs.channel_filling(48, 70.0, 29),      # tile width 32, pressure faces
+        inputs.random_small(40, 12, 10, seed=8, walls=True, open_x=True, optimised_model=True,
+                            u_amp=0.002, storage="fp32_shift"),   # tile width 16
+        inputs.droplet_on_wall(32, 150.0, 11),
+    ]
+
+
+def _steps(wl):
+    return wl.steps if wl.steps else 23
+
+
+def _alone(lbm, wl, n):
+    lat = lbm.Lattice(wl, storage="fp32_shift")
+    lat.step(n)
+    phi, P, u = lat.fields()
+    d = lat.diagnostics()
+    lat.close()
+    return phi, P, u, d
+
+
+def _serve(lbm, wls, **cfg):
+    srv = lbm.Server(storage="fp32_shift", **cfg)
+    tickets = [srv.submit(wl, _steps(wl)) for wl in wls]
+    srv.drain()
+    out = [srv.poll(t) for t in tickets]
+    srv.close()
+    return out
+
+
+def _check_same(lbm, wls, results):
+    for wl, r in zip(wls, results):
+        print("case", wl.name, wl.shape, "steps", _steps(wl), flush=True)
+        assert r is not None and r["status"] == lbm.LBM_OK, (wl.name, r and r["status"])
+        assert r["steps"] == _steps(wl)
+        phi, P, u, d = _alone(lbm, wl, _steps(wl))
+        assert np.array_equal(r["phi"], phi), wl.name
+        assert np.array_equal(r["P"], P), wl.name
+        assert np.array_equal(r["u"], u), wl.name
+        assert r["diag"]["phi_sum"] == d["phi_sum"], wl.name
+        assert r["diag"]["n_nan"] == 0
+
+
+def test_alone_equals_mix_bitwise_graph():
+    lbm = _lbm()
+    wls = _mix()
+    # the budget holds about two of the larger lattices: admission waits
+    budget = 2 * max(lbm.footprint(wl, "fp32_shift") for wl in wls) + (1 << 20)
+    res = _serve(lbm, wls, hbm_budget=budget, use_graph=True, ticks_per_sync=8)
+    _check_same(lbm, wls, res)
+
+
+def test_alone_equals_mix_bitwise_direct_launches_few_slots():
+    lbm = _lbm()
+    wls = _mix()[:4]
+    res = _serve(lbm, wls, hbm_budget=1 << 30, max_slots=2, use_graph=False, ticks_per_sync=6)
+    _check_same(lbm, wls, res)
+
+
+def test_budget_serialises_admission():
+    """With room for one lattice at a time, each request is admitted only
+    after the previous one finished, in submission order."""
+    lbm = _lbm()
+    from paper_2512_01032_amd import inputs
+    wls = [inputs.droplet_on_wall(32, 60.0 + 10 * k, 12 + 2 * k) for k in range(4)]
+    fp = lbm.footprint(wls[0], "fp32_shift")
+    srv = lbm.Server(storage="fp32_shift", hbm_budget=fp + fp // 2, ticks_per_sync=4)
+    tickets = [srv.submit(wl, wl.steps) for wl in wls]
+    srv.drain()
+    res = [srv.poll(t) for t in tickets]
+    srv.close()
+    for a, b in zip(res, res[1:]):
+        assert a["status"] == b["status"] == lbm.LBM_OK
+        assert b["t_admit"] >= a["t_finish"] >= a["t_admit"] >= a["t_submit"]
+
+
+def test_rejections_and_tickets():
+    lbm = _lbm()
+    from paper_2512_01032_amd import inputs
+    big = inputs.droplet_on_wall(48, 90.0, 4)
+    small = inputs.droplet_on_wall(32, 90.0, 4)
+    srv = lbm.Server(storage="fp32_shift", hbm_budget=lbm.footprint(small, "fp32_shift") + 4096)
+    with pytest.raises(lbm.LbmError) as ei:
+        srv.submit(big, 4)
+    assert ei.value.code == lbm.LBM_E_INVAL
+    with pytest.raises(lbm.LbmError):
+        srv.submit(small, 0)
+    t = srv.submit(small, 4)
+    deadline = time.time() + 60
+    r = srv.poll(t)
+    while r is None and time.time() < deadline:
+        time.sleep(0.01)
+        r = srv.poll(t)
+    assert r is not None and r["status"] == lbm.LBM_OK
+    with pytest.raises(lbm.LbmError):
+        srv.poll(t)          # a ticket is returned once
+    with pytest.raises(lbm.LbmError):
+        srv.poll(12345)
+    srv.close()
