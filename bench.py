@@ -137,6 +137,96 @@ def _finish_fold(rec):
     print(json.dumps(rec["bytes_per_sweep"]))
 
 
+def fluid_nodes(wl):
+    """Nodes that are updated: not solid, not on a pressure-face ghost layer."""
+    import numpy as np
+    m = np.ones(wl.shape, bool) if wl.solid is None else (wl.solid == 0)
+    for f, fc in enumerate(wl.faces):
+        if fc is None:
+            continue
+        ax = 2 - f // 2                        # arrays are [z, y, x]
+        idx = [slice(None)] * 3
+        idx[ax] = 0 if f % 2 == 0 else -1
+        m[tuple(idx)] = False
+    return int(m.sum())
+
+
+def _percentiles(lat):
+    import numpy as np
+    a = np.asarray(lat)
+    return float(np.percentile(a, 50)), float(np.percentile(a, 99))
+
+
+def serve_batched(trace, wls, budget_gb):
+    """Replay the trace in real time through the batched server."""
+    from paper_2512_01032_amd import lbm
+    srv = lbm.Server(storage="fp32_shift", hbm_budget=int(budget_gb * 1e9), use_graph=True,
+                     ticks_per_sync=32)
+    c0 = srv.clock()
+    w0 = time.perf_counter()
+    tickets = []
+    for r, wl in zip(trace, wls):
+        delay = r.arrival_s - (time.perf_counter() - w0)
+        if delay > 0:
+            time.sleep(delay)
+        tickets.append(srv.submit(wl, r.steps, arrival_s=r.arrival_s))
+    srv.drain()
+    lat, work, tf, bad = [], 0, 0.0, 0
+    for r, wl, t in zip(trace, wls, tickets):
+        res = srv.poll(t)
+        if res["status"] != lbm.LBM_OK:
+            bad += 1
+        lat.append(res["t_finish"] - (c0 + r.arrival_s))
+        tf = max(tf, res["t_finish"] - c0)
+        work += fluid_nodes(wl) * r.steps
+    srv.close()
+    p50, p99 = _percentiles(lat)
+    return {"budget_GB": budget_gb, "p50_s": p50, "p99_s": p99, "makespan_s": tf,
+            "mlups_aggregate": work / tf / 1e6, "failed": bad}
+
+
+def serve_one_at_a_time(trace, wls, torch):
+    """The same trace, FIFO, one lattice at a time through lbm_create/lbm_step."""
+    from paper_2512_01032_amd import lbm
+    stream = torch.cuda.current_stream()
+    w0 = time.perf_counter()
+    lat, work = [], 0
+    for r, wl in zip(trace, wls):
+        delay = r.arrival_s - (time.perf_counter() - w0)
+        if delay > 0:
+            time.sleep(delay)
+        L = lbm.Lattice(wl, storage="fp32_shift", stream=stream.cuda_stream)
+        L.step(r.steps)
+        L.fields()
+        L.close()
+        lat.append(time.perf_counter() - w0 - r.arrival_s)
+        work += fluid_nodes(wl) * r.steps
+    tf = time.perf_counter() - w0
+    p50, p99 = _percentiles(lat)
+    return {"p50_s": p50, "p99_s": p99, "makespan_s": tf, "mlups_aggregate": work / tf / 1e6}
+
+
+def serving_leg(args, torch):
+    from paper_2512_01032_amd import inputs
+    trace = inputs.serving_trace()[:args.serve_requests]
+    wls = [r.workload("fp32_shift") for r in trace]
+    total = sum(fluid_nodes(wl) * r.steps for r, wl in zip(trace, wls))
+    out = {"workload": "serving trace: %d requests, Poisson 50/s, droplet-on-wall e^3 or channel "
+                       "2e x e/2 x e/2, e in 32..128, 2000-10000 steps, FP32 shifted" % len(trace),
+           "fluid_node_updates": total, "batched": []}
+    for b in [float(x) for x in args.serve_budgets_gb.split(",") if x]:
+        print("[bench] serving: batched, budget %.3g GB" % b, file=sys.stderr, flush=True)
+        r = serve_batched(trace, wls, b)
+        print("[bench] serving: %s" % json.dumps(r), file=sys.stderr, flush=True)
+        out["batched"].append(r)
+    if not args.no_serve_baseline:
+        print("[bench] serving: one at a time", file=sys.stderr, flush=True)
+        r = serve_one_at_a_time(trace, wls, torch)
+        print("[bench] serving: %s" % json.dumps(r), file=sys.stderr, flush=True)
+        out["one_at_a_time"] = r
+    return out
+
+
 def run_gpu(wl, storage, steps, warmup, torch):
     from paper_2512_01032_amd import lbm
     stream = torch.cuda.current_stream()
@@ -173,6 +263,12 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (the calibration "
                          "kernel for the HBM byte counters)")
+    ap.add_argument("--serve-requests", type=int, default=256,
+                    help="requests of the serving trace to replay (0: skip the serving leg)")
+    ap.add_argument("--serve-budgets-gb", default="64,1",
+                    help="HBM budgets (GB) of the batched server runs")
+    ap.add_argument("--no-serve-baseline", action="store_true",
+                    help="skip the one-at-a-time replay of the serving trace")
     ap.add_argument("--fold-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="fold two rocprofv3 --pmc counter_collection.csv files (FETCH_SIZE, "
                          "WRITE_SIZE) into the per-launch traffic record and exit")
@@ -259,6 +355,8 @@ def main():
             g.close()
         del o
 
+    serving = serving_leg(args, torch) if args.serve_requests > 0 else None
+
     sh, sg = storage_bytes("fp32_shift")
     b_alg = 2 * (7 * sh + 19 * sg)
     traffic = measured_traffic("fp32_shift")
@@ -288,6 +386,7 @@ def main():
         "modes": {m: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
                   for m, r in results.items()},
         "max_abs_dphi_vs_oracle": errors,
+        "serving": serving,
         "kernel_hash": kernel_hash(),
     }
     print(json.dumps(line))

@@ -5,6 +5,23 @@
 
 namespace pflbm {
 
+// Step counter of every lattice in a descriptor table: t -> t+1 unless the
+// lattice has reached its stop step.  Launched once per time step, after the
+// ghost pass (the phi, sweep and ghost kernels all read the counter).
+__global__ void __launch_bounds__(NTHREADS) advance_kernel(Desc* __restrict__ descs, int nlat) {
+    const int k = blockIdx.x * NTHREADS + threadIdx.x;
+    if (k >= nlat) return;
+    Desc* D = descs + k;
+    const int64_t step = D->step;
+    if (step < D->stop_step) D->step = step + 1;
+}
+
+hipError_t launch_advance(Desc* d, int nlat, hipStream_t s) {
+    if (nlat <= 0) return hipSuccess;
+    advance_kernel<<<dim3((nlat + NTHREADS - 1) / NTHREADS), dim3(NTHREADS), 0, s>>>(d, nlat);
+    return hipGetLastError();
+}
+
 hipError_t launch_sweep_fp64(int, int, int, Desc*, const Tile*, int, int, ReadOut, InitIn, hipStream_t);
 hipError_t launch_phi_fp64(int, const Desc*, const Tile*, int, hipStream_t, int);
 hipError_t launch_restore_fp64(int, const Desc*, const Tile*, int, const double*, hipStream_t);

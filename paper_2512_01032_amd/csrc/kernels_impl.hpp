@@ -448,15 +448,29 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
 #pragma unroll
     for (int j = 0; j < NPART; ++j) acc[j] = 0.0;
 
+    // ring slot j holds plane z0 - 1 + j (mod 4).  The prologue stages the
+    // three planes the first node plane needs; each iteration issues the
+    // global loads of plane z+2 before its own work and writes them to the
+    // slot of plane z-2 (last read in the previous iteration) after it, so
+    // their latency overlaps the population traffic, and one barrier per
+    // plane orders the ring.
     stage(0, tl.z0 - 1);
     stage(1, tl.z0);
+    stage(2, tl.z0 + 1);
+    __syncthreads();
     const int c0 = (ty + 1) * LW + (tx + 1);
     for (int k = 0; k < tl.zn; ++k) {
         const int z = tl.z0 + k;
-        // a 4-plane ring needs one barrier per plane: a thread that runs ahead
-        // stages plane z+2 into the slot of z-2, which no thread still reads
-        stage(k + 2, z + 1);
-        __syncthreads();
+        const bool more = k + 1 < tl.zn;
+        T nv0 = T(0), nv1 = T(0);
+        uint8_t nf0 = 0, nf1 = 0;
+        if (more) {
+            const int zq = z + 2 >= nz ? z + 2 - nz : z + 2;
+            const int zo = zq * nxy;
+            if (tid < LN) { nv0 = phig[coff0 + zo]; nf0 = flg[coff0 + zo]; }
+            if (coff1 >= 0) { nv1 = phig[coff1 + zo]; nf1 = flg[coff1 + zo]; }
+        }
+        do {
         if (!active) continue;
         const int sm = k & 3, s0 = (k + 1) & 3, sp = (k + 2) & 3;
         const int n = x + nx * y + nxy * z;
@@ -778,13 +792,24 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
                 gbuf[2 * gc + slot] = st.u[2];
             }
         }
+        } while (0);
+        if (more) {
+            const int m = (k + 3) & 3;
+            if (tid < LN) { s_phi[m][tid] = nv0; s_flag[m][tid] = nf0; }
+            if (coff1 >= 0) { s_phi[m][tid + NTHREADS] = nv1; s_flag[m][tid + NTHREADS] = nf1; }
+        }
+        __syncthreads();
     }
 
-    if (MODE == MODE_INIT) return;
+    // Only a diagnostic pass needs tiles to meet: a cross-tile handshake costs
+    // an agent-scope release and acquire per tile (L2 write-back and
+    // invalidate on a chip whose XCDs have separate L2s).  The step counter
+    // advances in its own kernel.
+    if (MODE == MODE_INIT || !(DIAG && diag)) return;
 
     // ---- per-tile FP64 partials (wavefront shuffle -> LDS), then the last
     //      tile of the lattice reduces them in a fixed order
-    if (DIAG && diag) {
+    {
         const int lane = tid & 63, wv = tid >> 6;
 #pragma unroll
         for (int j = 0; j < NPART; ++j) {
@@ -809,7 +834,7 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
     __syncthreads();
     if (!s_last) return;
     __threadfence();
-    if (DIAG && diag) {
+    {
         // fixed-order reduction: thread t sums tiles t, t+256, ... then a tree
         const int nt = uni(D->ntiles);
         for (int j = 0; j < NPART; ++j) {
@@ -837,11 +862,9 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
             if (nan || fast) D->unstable = 1;
         }
     }
-    if (tid == 0) {
-        if (MODE == MODE_STEP) D->step = step + 1;
-        __hip_atomic_store(D->counter, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    if (tid == 0) __hip_atomic_store(D->counter, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
+
 
 // --------------------------------------------------------------- restore
 // Populations f_i(x) of a step of parity PAR (canonical [26][N] doubles) into
@@ -886,7 +909,7 @@ restore_kernel(const Desc* __restrict__ descs, const Tile* __restrict__ tiles,
 // t+1, without forcing and without the counter-term.  Only the directions
 // that point into a fluid node are written, into the slots the next step's
 // parity reads: (g + c_i, i) for an even step, (g, opp(i)) for an odd one.
-// Runs after the sweep, which has advanced the step counter to t+1.
+// Runs after the sweep of step t and before the step counter advances.
 template <typename T, typename SH, typename SG>
 __global__ void __launch_bounds__(NTHREADS)
 ghost_kernel(const Desc* __restrict__ descs, const GhostRef* __restrict__ ghosts, int nghosts) {
@@ -894,7 +917,9 @@ ghost_kernel(const Desc* __restrict__ descs, const GhostRef* __restrict__ ghosts
     if (k >= nghosts) return;
     const GhostRef gr = ghosts[k];
     const Desc* D = descs + gr.lat;
-    const int64_t next = D->step;                 // step t+1
+    const int64_t step = D->step;
+    if (step >= D->stop_step) return;
+    const int64_t next = step + 1;
     const int par = (int)(next & 1);
     const int nx = D->nx, ny = D->ny, nz = D->nz;
     const int64_t N = D->N;

@@ -174,6 +174,7 @@ extern "C" int lbm_step(lbm_handle* h, int64_t nsteps) {
                             h->stream));
         if (h->nghosts)
             HIPRET(launch_ghosts(storage, h->ddesc, h->dghosts, h->nghosts, h->stream));
+        HIPRET(launch_advance(h->ddesc, 1, h->stream));
         if (h->timing) HIPRET(hipEventRecord(e2, h->stream));
     }
     h->step += nsteps;

@@ -149,6 +149,7 @@ hipError_t launch_restore(int storage, int parity, const Desc* d, const Tile* ti
                           const double* pops, hipStream_t s);
 // after a sweep: equilibrium populations of every listed pressure ghost for
 // the next step (the step counter the sweep advanced), from its owner's u
+hipError_t launch_advance(Desc* d, int nlat, hipStream_t s);
 hipError_t launch_ghosts(int storage, const Desc* d, const GhostRef* ghosts, int nghosts,
                          hipStream_t s);
 

@@ -290,6 +290,7 @@ hipError_t enqueue_steps(lbm_server* s) {
                                  ro, in, s->stream);
         if (e == hipSuccess && s->nghosts)
             e = launch_ghosts(storage, s->dtable, s->dghosts, s->nghosts, s->stream);
+        if (e == hipSuccess) e = launch_advance(s->dtable, s->table_slots, s->stream);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -473,6 +474,9 @@ extern "C" int lbm_server_create(const lbm_server_cfg* cfg, lbm_server** out) {
         set_error("server set-up: %s", hipGetErrorString(e));
         return cleanup(rc);
     }
+    // unused slots read as stopped (step 0, stop step 0) by the advance pass
+    e = hipMemset(s->dtable, 0, (size_t)s->cfg.max_slots * sizeof(Desc));
+    if (e != hipSuccess) return cleanup(device_error("hipMemset", e));
     s->arena_bytes = budget;
     s->alloc.reset(budget);
     for (int i = s->cfg.max_slots - 1; i >= 0; --i) s->free_slots.push_back(i);
