@@ -108,9 +108,12 @@ int choose_tz(const lbm_params* p, int tx) {
     if (env && atoi(env) > 0) return std::min(atoi(env), p->nz);
     const int ty = NTHREADS / tx;
     const int64_t cols = (int64_t)((p->nx + tx - 1) / tx) * ((p->ny + ty - 1) / ty);
-    // deepest chunk that still gives >= 8 tiles per compute unit (256 CUs)
-    int tz = 64;
-    while (tz > 4 && cols * ((p->nz + tz - 1) / tz) < 2048) tz /= 2;
+    // Short z-chunks: a tile's set-up (three staged phi planes) is cheap, and
+    // many more tiles than resident blocks (4 per CU x 256 CUs) leave no
+    // half-empty last round.  8 planes, halved down to 2 until the lattice has
+    // >= 4096 tiles.
+    int tz = 8;
+    while (tz > 2 && cols * ((p->nz + tz - 1) / tz) < 4096) tz /= 2;
     return std::min(tz, p->nz);
 }
 
