@@ -206,6 +206,66 @@ def serve_one_at_a_time(trace, wls, torch):
     return {"p50_s": p50, "p99_s": p99, "makespan_s": tf, "mlups_aggregate": work / tf / 1e6}
 
 
+def accuracy_leg(storages):
+    """Errors of each storage mode against the FP64 oracle on the small
+    validation cases: the static droplet (phi after 200 steps; Laplace
+    pressure after 3000 steps against the oracle and 2 sigma / R), and the
+    equilibrium contact angle of quasi-2D wall caps after 8000 steps."""
+    import numpy as np
+    from paper_2512_01032_amd import inputs, lbm
+    from oracle import measure, ref, theory
+    out = {m: {} for m in storages}
+
+    def laplace(d, sigma):
+        R = (3.0 * d["phi_sum"] / (4.0 * np.pi)) ** (1.0 / 3.0)
+        return d["P_liq_mean"] - d["P_gas_mean"], theory.laplace_pressure(sigma, R)
+
+    wl = inputs.static_droplet()
+    print("[bench] accuracy: static droplet, oracle 3000 steps", file=sys.stderr, flush=True)
+    o = ref.Oracle(wl)
+    o.step(200)
+    phi200 = o.fields()[0]
+    o.step(2800)
+    dP_o, dP_th = laplace(o.diagnostics(), wl.phys.sigma)
+    for m in storages:
+        g = lbm.Lattice(wl, storage=m)
+        g.step(200)
+        e200 = float(np.abs(g.fields()[0] - phi200).max())
+        g.step(2800)
+        dP_g, dP_gth = laplace(g.diagnostics(), wl.phys.sigma)
+        g.close()
+        out[m]["static_droplet"] = {
+            "max_abs_dphi_200_steps": e200,
+            "dP_3000_steps": dP_g, "dP_oracle": dP_o, "dP_theory_2sigma_over_R": dP_gth,
+            "laplace_rel_err_vs_oracle": abs(dP_g - dP_o) / abs(dP_o),
+            "laplace_rel_err_vs_theory": abs(dP_g - dP_gth) / dP_gth}
+    for theta in (60.0, 120.0):
+        wl = inputs.wall_cap_2d(theta)
+        print("[bench] accuracy: wall cap %g deg, oracle 8000 steps" % theta, file=sys.stderr,
+              flush=True)
+
+        def angle(phi):
+            pts = measure.contour_points_xz(phi[:, 0, :], z_min=1)
+            pts = pts[pts[:, 1] > 2.5]
+            xc, zc, Rf = measure.fit_circle(pts)
+            return theory.cap_angle_from_circle(zc, Rf, wl.meta["wall_z"])
+        o = ref.Oracle(wl)
+        o.step(wl.steps)
+        phi_o = o.fields()[0]
+        a_o = angle(phi_o)
+        for m in storages:
+            g = lbm.Lattice(wl, storage=m)
+            g.step(wl.steps)
+            phi_g = g.fields()[0]
+            g.close()
+            a_g = angle(phi_g)
+            out[m]["cap_%g" % theta] = {
+                "angle_deg": a_g, "angle_oracle_deg": a_o,
+                "angle_err_vs_oracle_deg": abs(a_g - a_o), "angle_err_vs_input_deg": abs(a_g - theta),
+                "max_abs_dphi": float(np.abs(phi_g - phi_o).max())}
+    return out
+
+
 def serving_leg(args, torch):
     from paper_2512_01032_amd import inputs
     trace = inputs.serving_trace()[:args.serve_requests]
@@ -324,9 +384,9 @@ def main():
             del lattices[m]
 
     primary = results["fp32_shift"]
-    info_nf = None
     cpu = None
     errors = {}
+    accuracy = None
     if not args.no_cpu_baseline:
         # FP64 oracle on the host cores, bounded sample: this lattice, a few
         # steps; the same steps on the GPU give max |phi - oracle|
@@ -354,6 +414,7 @@ def main():
             errors[m] = float(np.abs(phi_g - phi_o)[fluid].max())
             g.close()
         del o
+        accuracy = accuracy_leg(("fp32_shift", "fp16_shift_g", "fp64"))
 
     serving = serving_leg(args, torch) if args.serve_requests > 0 else None
 
@@ -386,6 +447,7 @@ def main():
         "modes": {m: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
                   for m, r in results.items()},
         "max_abs_dphi_vs_oracle": errors,
+        "accuracy_vs_oracle": accuracy,
         "serving": serving,
         "kernel_hash": kernel_hash(),
     }

@@ -205,6 +205,24 @@ def constricted_duct(nx=256, ny=256, nz=512, step_z=256, theta=120.0, ramp_to=2e
                     meta={"slugs": slugs, "step_z": step_z})
 
 
+def wall_cap_2d(theta, nx=64, nz=24, R=11.0, W=4.0, steps=8000, storage="fp64"):
+    """Quasi-2D cylindrical cap (y of width 1, periodic) on a wall at z = 0
+    (material 0, angle theta) under a neutral wall at z = nz - 1, centred at
+    x = (nx - 1)/2, initial radius R about the wall plane z = 0.5; Sec. II
+    model."""
+    ph = Physics(W=W)
+    x, y, z = _grid(nx, 1, nz)
+    r = np.sqrt((x - (nx - 1) / 2.0) ** 2 + (z - 0.5) ** 2)
+    solid = np.zeros((nz, 1, nx), np.uint8)
+    solid[0] = 1
+    solid[nz - 1] = 2
+    th = [90.0] * 16
+    th[0] = theta
+    return Workload("cap2d_%g" % theta, nx, 1, nz, ph, tanh_profile(r - R, W), solid=solid,
+                    theta_deg=tuple(th), steps=steps, storage=storage,
+                    meta={"theta": theta, "wall_z": 0.5})
+
+
 # --------------------------------------------------------------------------- C5
 def droplet_on_wall(e, theta, steps, storage="fp32_shift", W=4.0):
     ph = optimised(Physics(W=W, nu_g=visc_ratio_nu_g(0.01, 1.0, 0.001, 100.0)))

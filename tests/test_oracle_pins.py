@@ -366,17 +366,7 @@ def test_equilibrium_contact_angle_2d_cap(theta):
     """A cylindrical cap on a flat wall (quasi-2D, y periodic of width 1)
     relaxes to the input angle, measured by a circle fit of the phi = 0.5
     contour (Sec. IV.A).  Sec. II model, W = 4."""
-    nx, nz, R = 64, 24, 11.0
-    ph = I.Physics(W=4.0)
-    x, y, z = I._grid(nx, 1, nz)
-    r = np.sqrt((x - (nx - 1) / 2) ** 2 + (z - 0.5) ** 2)
-    solid = np.zeros((nz, 1, nx), np.uint8)
-    solid[0] = 1
-    solid[nz - 1] = 2
-    th = [90.0] * 16
-    th[0] = theta
-    wl = I.Workload("cap", nx, 1, nz, ph, I.tanh_profile(r - R, 4.0), solid=solid,
-                    theta_deg=tuple(th))
+    wl = I.wall_cap_2d(theta)
     o = ref.Oracle(wl)
     o.step(8000)
     phi = o.fields()[0][:, 0, :]
