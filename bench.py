@@ -157,11 +157,11 @@ def _percentiles(lat):
     return float(np.percentile(a, 50)), float(np.percentile(a, 99))
 
 
-def serve_batched(trace, wls, budget_gb):
+def serve_batched(trace, wls, budget_gb, cap_nodes):
     """Replay the trace in real time through the batched server."""
     from paper_2512_01032_amd import lbm
     srv = lbm.Server(storage="fp32_shift", hbm_budget=int(budget_gb * 1e9), use_graph=True,
-                     ticks_per_sync=32)
+                     ticks_per_sync=32, max_resident_nodes=int(cap_nodes))
     c0 = srv.clock()
     w0 = time.perf_counter()
     tickets = []
@@ -181,8 +181,8 @@ def serve_batched(trace, wls, budget_gb):
         work += fluid_nodes(wl) * r.steps
     srv.close()
     p50, p99 = _percentiles(lat)
-    return {"budget_GB": budget_gb, "p50_s": p50, "p99_s": p99, "makespan_s": tf,
-            "mlups_aggregate": work / tf / 1e6, "failed": bad}
+    return {"budget_GB": budget_gb, "max_resident_nodes": int(cap_nodes), "p50_s": p50,
+            "p99_s": p99, "makespan_s": tf, "mlups_aggregate": work / tf / 1e6, "failed": bad}
 
 
 def serve_one_at_a_time(trace, wls, torch):
@@ -274,9 +274,11 @@ def serving_leg(args, torch):
     out = {"workload": "serving trace: %d requests, Poisson 50/s, droplet-on-wall e^3 or channel "
                        "2e x e/2 x e/2, e in 32..128, 2000-10000 steps, FP32 shifted" % len(trace),
            "fluid_node_updates": total, "batched": []}
-    for b in [float(x) for x in args.serve_budgets_gb.split(",") if x]:
-        print("[bench] serving: batched, budget %.3g GB" % b, file=sys.stderr, flush=True)
-        r = serve_batched(trace, wls, b)
+    for leg in [x for x in args.serve_legs.split(",") if x]:
+        b, cap = (float(v) for v in leg.split(":"))
+        print("[bench] serving: batched, budget %.3g GB, resident-node cap %.3g" % (b, cap),
+              file=sys.stderr, flush=True)
+        r = serve_batched(trace, wls, b, cap)
         print("[bench] serving: %s" % json.dumps(r), file=sys.stderr, flush=True)
         out["batched"].append(r)
     if not args.no_serve_baseline:
@@ -325,8 +327,9 @@ def main():
                          "kernel for the HBM byte counters)")
     ap.add_argument("--serve-requests", type=int, default=256,
                     help="requests of the serving trace to replay (0: skip the serving leg)")
-    ap.add_argument("--serve-budgets-gb", default="64,1",
-                    help="HBM budgets (GB) of the batched server runs")
+    ap.add_argument("--serve-legs", default="64:16e6,1:0",
+                    help="batched server runs as budget_GB:max_resident_nodes pairs "
+                         "(0 nodes: no cap)")
     ap.add_argument("--no-serve-baseline", action="store_true",
                     help="skip the one-at-a-time replay of the serving trace")
     ap.add_argument("--fold-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),

@@ -216,8 +216,10 @@ typedef struct lbm_server_cfg {
     int32_t max_slots;       /* lattices resident at once (<= 256) */
     int32_t storage;         /* enum lbm_storage used by every request */
     int32_t device;
-    int32_t use_graph;       /* 1: capture the tick in a hipGraph */
-    int32_t ticks_per_sync;  /* ticks queued between host scheduling points (>= 1) */
+    int32_t use_graph;       /* 1: replay each scheduling interval from a captured hipGraph */
+    int32_t ticks_per_sync;  /* steps per scheduling interval, rounded up to even (0: 32) */
+    int64_t max_resident_nodes; /* admission also waits while the resident lattices hold more
+                                   nodes than this, unless none is resident (0: no limit) */
 } lbm_server_cfg;
 
 typedef struct lbm_request {

@@ -1,8 +1,10 @@
 // serve.hip -- continuous batching of independent lattices on one GPU.
 //
 // A worker thread owns the GPU side.  Requests wait in a FIFO queue; the head
-// is admitted when a descriptor slot is free and its footprint fits in a
-// free block of the server's HBM arena.  Every admitted lattice starts at
+// is admitted when a descriptor slot is free, its footprint fits in a free
+// block of the server's HBM arena and the resident node count stays within
+// the configured cap (admitting more than fills the GPU only slows every
+// resident lattice down).  Every admitted lattice starts at
 // step 0.  Work proceeds in scheduling intervals of an even number of steps:
 // each step is one phi launch over the concatenated tile tables of all
 // resident lattices, one sweep launch per tile width and one ghost launch.
@@ -120,6 +122,7 @@ struct lbm_server {
     struct Group { int tx, off, n; };
     std::vector<Group> groups;
     int ntiles = 0, nghosts = 0, table_slots = 0;
+    int64_t resident_nodes = 0;
     bool dirty = true;
     hipGraphExec_t gexec = nullptr;
     // jobs
@@ -184,7 +187,9 @@ int admit_one(lbm_server* s) {
         job->laid_out = true;
         job->bytes = job->L.total;
     }
-    if (s->free_slots.empty() || !s->alloc.alloc(job->bytes, &job->off)) {
+    const bool over_cap = s->cfg.max_resident_nodes > 0 && !s->active.empty() &&
+                          s->resident_nodes + job->L.N > s->cfg.max_resident_nodes;
+    if (over_cap || s->free_slots.empty() || !s->alloc.alloc(job->bytes, &job->off)) {
         if (s->active.empty()) {
             // nothing will be freed: the request can never be placed
             set_error("request of %zu bytes does not fit the arena", job->bytes);
@@ -227,6 +232,7 @@ int admit_one(lbm_server* s) {
     job->geo.solid = nullptr;
     job->t_admit = s->now();
     job->step = 0;
+    s->resident_nodes += job->L.N;
     s->active.push_back(std::move(job));
     s->dirty = true;
     return 1;
@@ -358,6 +364,7 @@ int finalize(lbm_server* s, std::unique_ptr<Job> job) {
     }
     s->alloc.release(job->off, job->bytes);
     s->free_slots.push_back(job->slot);
+    s->resident_nodes -= job->L.N;
     s->dirty = true;
     finish_job(s, std::move(job));
     return LBM_OK;
@@ -438,6 +445,7 @@ extern "C" int lbm_server_create(const lbm_server_cfg* cfg, lbm_server** out) {
         return LBM_E_INVAL;
     }
     if (cfg->ticks_per_sync < 0) { set_error("ticks_per_sync < 0"); return LBM_E_INVAL; }
+    if (cfg->max_resident_nodes < 0) { set_error("max_resident_nodes < 0"); return LBM_E_INVAL; }
     std::unique_ptr<lbm_server> s(new (std::nothrow) lbm_server());
     if (!s) { set_error("host allocation failed"); return LBM_E_NOMEM; }
     s->cfg = *cfg;

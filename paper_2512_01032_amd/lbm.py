@@ -73,7 +73,8 @@ class lbm_info(ctypes.Structure):
 
 class lbm_server_cfg(ctypes.Structure):
     _fields_ = [("hbm_budget", c_size_t), ("max_slots", c_int32), ("storage", c_int32),
-                ("device", c_int32), ("use_graph", c_int32), ("ticks_per_sync", c_int32)]
+                ("device", c_int32), ("use_graph", c_int32), ("ticks_per_sync", c_int32),
+                ("max_resident_nodes", c_int64)]
 
 
 class lbm_request(ctypes.Structure):
@@ -294,7 +295,7 @@ class Server:
     """Continuous-batching server through the C ABI (lbm_server_*)."""
 
     def __init__(self, storage="fp32_shift", hbm_budget=0, max_slots=0, use_graph=True,
-                 ticks_per_sync=32, device=0):
+                 ticks_per_sync=32, device=0, max_resident_nodes=0):
         cfg = lbm_server_cfg()
         cfg.hbm_budget = int(hbm_budget)
         cfg.max_slots = int(max_slots)
@@ -302,6 +303,7 @@ class Server:
         cfg.device = int(device)
         cfg.use_graph = int(bool(use_graph))
         cfg.ticks_per_sync = int(ticks_per_sync)
+        cfg.max_resident_nodes = int(max_resident_nodes)
         h = ctypes.c_void_p()
         check(lbm_server_create(ctypes.byref(cfg), ctypes.byref(h)))
         self.h = h
