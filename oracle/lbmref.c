@@ -255,7 +255,8 @@ static void stencil(const lbmref_state *s, long n, double grad[3], double *lap) 
         const double *nw = &s->nw[3 * n];
         double g0[3] = {0.0, 0.0, 0.0};
         for (int i = 1; i < 19; ++i)
-            for (int a = 0; a < 3; ++a) g0[a] += WG[i] * CV[i][a] * ph[i] / TG;
+            for (int a = 0; a < 3; ++a) g0[a] += (ph[i] - ph[s->opp[i]]) * CV[i][a] * WG[i];
+        for (int a = 0; a < 3; ++a) g0[a] /= 2.0 * TG;
         for (int i = 1; i < 19; ++i) {
             if (!sol[i]) continue;
             long m = neighbour(s, n, i, +1);
@@ -264,13 +265,15 @@ static void stencil(const lbmref_state *s, long n, double grad[3], double *lap) 
             ph[i] = lbmref_wet_phi_s(pc, w, CV[i], p->W, p->clamp_a);
         }
     }
-    /* Eq. 16; summing over all i doubles each +-c pair, hence 1/T instead of 1/(2T) */
+    /* Eq. 16 as printed: gradient from the differences phi(x + c_i) - phi(x - c_i)
+     * over all i (each +-c pair twice) divided by 2T; Laplacian from
+     * phi(x + c_i) - phi(x) */
     double gsum[3] = {0.0, 0.0, 0.0}, l = 0.0;
     for (int i = 1; i < 19; ++i) {
-        for (int a = 0; a < 3; ++a) gsum[a] += WG[i] * CV[i][a] * ph[i];
-        l += WG[i] * (ph[i] - pc);
+        for (int a = 0; a < 3; ++a) gsum[a] += (ph[i] - ph[s->opp[i]]) * CV[i][a] * WG[i];
+        l += (ph[i] - pc) * WG[i];
     }
-    for (int a = 0; a < 3; ++a) grad[a] = gsum[a] / TG;
+    for (int a = 0; a < 3; ++a) grad[a] = gsum[a] / (2.0 * TG);
     *lap = 2.0 * l / TG;
 }
 

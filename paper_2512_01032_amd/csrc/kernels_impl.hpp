@@ -500,38 +500,44 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
         const T pc = s_phi[s0][c0];
         st.pc = pc;
 
-        // ---- gradient and Laplacian (Eq. 16) over the 18 neighbours
-        T gx = T(0), gy = T(0), gz = T(0), lap = T(0);
-#pragma unroll
-        for (int i = 1; i < 19; ++i) {
+        // ---- gradient and Laplacian (Eq. 16) in the paper's difference form,
+        //      sum_i (phi(x + c_i) - phi(x - c_i)) c_i w_i / (2T), each +-c pair
+        //      once (hence 1/T): a neighbourhood symmetric about x gives an
+        //      exactly zero component, which the eps-regularised unit vectors
+        //      (normal, wall tangent) would otherwise turn into O(1) noise
+        auto nbv = [&](int i) -> T {
             const int sl = CZ[i] < 0 ? sm : (CZ[i] > 0 ? sp : s0);
-            const T v = s_phi[sl][c0 + CY[i] * LW + CX[i]];
-            if (CX[i]) gx += T(wg(i) * CX[i]) * v;
-            if (CY[i]) gy += T(wg(i) * CY[i]) * v;
-            if (CZ[i]) gz += T(wg(i) * CZ[i]) * v;
-            lap += T(wg(i)) * (v - pc);
-        }
+            return s_phi[sl][c0 + CY[i] * LW + CX[i]];
+        };
+        T gx = T(0), gy = T(0), gz = T(0), lap = T(0);
+        auto pair_sum = [&](int i, T vp, T vm) {
+            const T dv = vp - vm;
+            if (CX[i]) gx += T(wg(i) * CX[i]) * dv;
+            if (CY[i]) gy += T(wg(i) * CY[i]) * dv;
+            if (CZ[i]) gz += T(wg(i) * CZ[i]) * dv;
+            lap += T(wg(i)) * ((vp - pc) + (vm - pc));
+        };
+#pragma unroll
+        for (int i = 1; i < 19; i += 2) pair_sum(i, nbv(i), nbv(i + 1));
         T nw[3] = {T(0), T(0), T(0)};
         if (solid) {
-            // wetting (Eqs. 17-19).  Pre-gradient with the node's own phi at
-            // the solid links; wall normal into the fluid from the solid links;
-            // w = -cos(theta) n + sin(theta) t with t the unit tangential part of
-            // the pre-gradient; phi_s,i from the tanh profile through phi(x)
-            // shifted by d_i = w . c_i; the stencil sums take phi_s,i there
-            T dgx = T(0), dgy = T(0), dgz = T(0), dl = T(0);
+            // wetting (Eqs. 17-19).  Wall normal into the fluid from the solid
+            // links; neutral pre-gradient (the node's own phi at the solid
+            // links); w = -cos(theta) n + sin(theta) t with t the unit
+            // tangential part of the pre-gradient; phi_s,i from the tanh
+            // profile through phi(x) shifted by d_i = w . c_i; the stencil is
+            // evaluated again with phi_s,i at the solid links
             for (int i = 1; i < 19; ++i) {
                 if (!((solid >> i) & 1u)) continue;
-                const int cx = CX[i], cy = CY[i], cz = CZ[i];
-                const int sl = cz < 0 ? sm : (cz > 0 ? sp : s0);
-                const T d = T(wg(i)) * (pc - s_phi[sl][c0 + cy * LW + cx]);
-                dgx += d * T(cx); dgy += d * T(cy); dgz += d * T(cz);
-                dl += d;
-                nw[0] -= T(wg(i) * cx); nw[1] -= T(wg(i) * cy); nw[2] -= T(wg(i) * cz);
+                nw[0] -= T(wg(i) * CX[i]); nw[1] -= T(wg(i) * CY[i]); nw[2] -= T(wg(i) * CZ[i]);
             }
-            gx += dgx; gy += dgy; gz += dgz; lap += dl;
             const T nn = dev_sqrt(nw[0] * nw[0] + nw[1] * nw[1] + nw[2] * nw[2]);
             const T inn = nn > T(0) ? T(1) / nn : T(0);
             nw[0] *= inn; nw[1] *= inn; nw[2] *= inn;
+            gx = gy = gz = lap = T(0);
+#pragma unroll
+            for (int i = 1; i < 19; i += 2)
+                pair_sum(i, ((solid >> i) & 1u) ? pc : nbv(i), ((solid >> (i + 1)) & 1u) ? pc : nbv(i + 1));
             const T g0[3] = {gx * iTg, gy * iTg, gz * iTg};
             const T ng = nw[0] * g0[0] + nw[1] * g0[1] + nw[2] * g0[2];
             T gt[3] = {g0[0] - nw[0] * ng, g0[1] - nw[1] * ng, g0[2] - nw[2] * ng};
@@ -542,9 +548,7 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
             a = a > T(1) - ph[PI_CLAMP_A] ? T(1) - ph[PI_CLAMP_A] : a;
             a = a < -T(1) + ph[PI_CLAMP_A] ? -T(1) + ph[PI_CLAMP_A] : a;
             const T k2W = ph[PI_K2W];
-            T egx = T(0), egy = T(0), egz = T(0), el = T(0);
-            for (int i = 1; i < 19; ++i) {
-                if (!((solid >> i) & 1u)) continue;
+            auto phis = [&](int i) -> T {
                 const int cx = CX[i], cy = CY[i], cz = CZ[i];
                 const int sl = cz < 0 ? sm : (cz > 0 ? sp : s0);
                 const int mat = flag_sub(s_flag[sl][c0 + cy * LW + cx]);
@@ -553,12 +557,14 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
                             sn * (gt[0] * T(cx) + gt[1] * T(cy) + gt[2] * T(cz));
                 const T t = dev_tanh(k2W * d);
                 // tanh(artanh(a) + 2d/W) by the addition theorem
-                const T ps = T(0.5) * (T(1) + (a + t) / (T(1) + a * t));
-                const T w = T(wg(i)) * (ps - pc);
-                egx += w * T(cx); egy += w * T(cy); egz += w * T(cz);
-                el += w;
+                return T(0.5) * (T(1) + (a + t) / (T(1) + a * t));
+            };
+            gx = gy = gz = lap = T(0);
+            for (int i = 1; i < 19; i += 2) {
+                const T vp = ((solid >> i) & 1u) ? phis(i) : nbv(i);
+                const T vm = ((solid >> (i + 1)) & 1u) ? phis(i + 1) : nbv(i + 1);
+                pair_sum(i, vp, vm);
             }
-            gx += egx; gy += egy; gz += egz; lap += el;
         }
         st.grad[0] = gx * iTg; st.grad[1] = gy * iTg; st.grad[2] = gz * iTg;
         lap = T(6) * lap;

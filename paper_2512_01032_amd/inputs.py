@@ -174,11 +174,14 @@ def slug_positions(seed=0, start=16, end=256, lo=20, hi=60):
 
 
 def constricted_duct(nx=256, ny=256, nz=512, step_z=256, theta=120.0, ramp_to=2e-3,
-                     ramp_steps=10000, seed=0, steps=10000, storage="fp32_shift", W=4.0):
+                     ramp_steps=10000, seed=0, steps=10000, storage="fp32_shift", W=4.0,
+                     slug_offset=0.0):
     """Square duct along z with walls at x, y in {0, n-1}; from z = step_z on,
     only the centred half-width square is fluid.  z = 0 is a pressure inlet
     ramped linearly by ramp_to over ramp_steps, z = nz-1 an outlet at P_ref.
-    Liquid slugs of seeded random length and spacing sit in the wide part."""
+    Liquid slugs of seeded random length and spacing sit in the wide part;
+    slug_offset shifts every slug end along z (a non-zero fraction of a cell
+    leaves no slug mid-plane on a node)."""
     ph = optimised(Physics(W=W, nu_g=visc_ratio_nu_g(0.01, 1.0, 0.001, 100.0)))
     solid = np.zeros((nz, ny, nx), np.uint8)
     solid[:, 0, :] = 1
@@ -194,7 +197,8 @@ def constricted_duct(nx=256, ny=256, nz=512, step_z=256, theta=120.0, ramp_to=2e
     zc = np.arange(nz, dtype=np.float64)
     phz = np.zeros(nz)
     for a, b in slugs:
-        phz += 0.5 * (np.tanh((zc - (a - 0.5)) / (0.5 * W)) - np.tanh((zc - (b - 0.5)) / (0.5 * W)))
+        za, zb = a - 0.5 + slug_offset, b - 0.5 + slug_offset
+        phz += 0.5 * (np.tanh((zc - za) / (0.5 * W)) - np.tanh((zc - zb) / (0.5 * W)))
     phz = np.clip(phz, 0.0, 1.0)
     phi0 = np.broadcast_to(phz[:, None, None], (nz, ny, nx)).copy()
     th = [90.0] * 16

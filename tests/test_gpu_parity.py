@@ -196,3 +196,134 @@ def test_unstable_flag_from_seeded_nan():
     with pytest.raises(lbm.LbmError) as ei:
         g.sync()
     assert ei.value.code == lbm.LBM_E_UNSTABLE
+
+
+# ------------------------------------------------ full-size configurations
+# The three lattice workloads at their full sizes, in the launch
+# configuration the benchmark times (tile shape chosen by the library for the
+# lattice), compared node by node with the oracle after a few steps.
+
+def _full(name):
+    from paper_2512_01032_amd import inputs
+    return {"sessile": inputs.sessile_droplet, "filling": inputs.capillary_filling,
+            "duct": inputs.constricted_duct}[name]()
+
+
+_DUCT_STEPS = 3
+
+
+def _duct(slug_offset=0.0):
+    from paper_2512_01032_amd import inputs
+    return inputs.constricted_duct(slug_offset=slug_offset)
+
+
+def _snapshot(o):
+    phi, P, u = o.fields()
+    h, g = o.pops()
+    return {"phi": phi, "P": P, "u": u, "h": h, "g": g, "diag": o.diagnostics()}
+
+
+@pytest.fixture(scope="module")
+def duct_oracle():
+    """The constricted duct stepped by the oracle once for this module (its
+    FP64 state is 15 GB of host memory); the full state after 3 steps."""
+    from oracle import ref
+    require_gpu()
+    wl = _duct()
+    o = ref.Oracle(wl)
+    o.step(_DUCT_STEPS)
+    snap = _snapshot(o)
+    kinds = o.kinds()
+    del o
+    return wl, kinds, snap
+
+
+def _check_fp64_arrays(g, snap, kinds, name, tol=FP64_TOL):
+    fluid = kinds == 0
+    pg, Pg, ug = g.fields()
+    hg, gg = g.pops()
+    err = {"phi": rel_err(pg, snap["phi"], fluid), "P": rel_err(Pg, snap["P"], fluid),
+           "h": rel_err(hg, snap["h"], fluid), "g": rel_err(gg, snap["g"], fluid)}
+    print(name, err, flush=True)
+    for k, v in err.items():
+        assert v <= tol, (k, v)
+    # sum of phi: the per-node bound, summed over the lattice
+    dg, do = g.diagnostics(), snap["diag"]
+    assert abs(dg["phi_sum"] - do["phi_sum"]) <= tol * abs(do["phi_sum"])
+
+
+def _check_fp64(g, o, name):
+    err = compare_state(g, o, o.kinds())
+    print(name, err, flush=True)
+    for k in ("phi", "P", "h", "g", "mom"):
+        assert err[k] <= FP64_TOL, (k, err[k])
+    dg, do = g.diagnostics(), o.diagnostics()
+    assert abs(dg["phi_sum"] - do["phi_sum"]) <= FP64_TOL * abs(do["phi_sum"])
+    assert dg["n_nan"] == 0 and dg["n_liq"] == do["n_liq"] and dg["n_gas"] == do["n_gas"]
+
+
+@pytest.mark.parametrize("name,steps", [("sessile", 4), ("filling", 5)])
+def test_full_size_fp64(name, steps):
+    g, o = _run_pair(_full(name), steps, "fp64")
+    _check_fp64(g, o, name)
+
+
+@pytest.mark.timeout(400)
+def test_full_size_duct_fp64_first_step(duct_oracle):
+    """The benchmark's duct in FP64: 1e-10 after the first step (against the
+    oracle's state after step 1, taken from a separate oracle run)."""
+    from oracle import ref
+    wl, kinds, snap3 = duct_oracle
+    lbm = _lbm()
+    print("case duct fp64 step 1", flush=True)
+    o = ref.Oracle(wl)
+    o.step(1)
+    snap = _snapshot(o)
+    del o
+    g = lbm.Lattice(wl, storage="fp64")
+    g.step(1)
+    _check_fp64_arrays(g, snap, kinds, "duct step 1")
+    g.close()
+
+
+@pytest.mark.timeout(400)
+def test_full_size_duct_fp64_offset_slugs():
+    """FP64 duct with the slug ends a quarter cell off the nodes, 1e-10 after
+    3 steps.  With the slugs on the nodes (the benchmark input) the slugs'
+    mid-planes and the cross-section's diagonals are exact symmetry planes
+    through nodes where 0 < phi < 1: there the normal grad/(|grad| + eps),
+    the wall tangent g_t/(|g_t| + eps) and the sign lap/(|lap| + eps) of the
+    mobility correction divide a vanishing quantity by |.| + 1e-10, so two
+    correct FP64 evaluations that sum symmetric terms in different orders
+    part by their rounding residue times 1e10 (2e-7 relative in phi after 3
+    steps).  Off the nodes every such argument is O(1e-5) and the two agree
+    to rounding."""
+    from oracle import ref
+    lbm = _lbm()
+    wl = _duct(slug_offset=0.25)
+    print("case duct fp64 offset slugs steps %d" % _DUCT_STEPS, flush=True)
+    o = ref.Oracle(wl)
+    o.step(_DUCT_STEPS)
+    snap = _snapshot(o)
+    kinds = o.kinds()
+    del o
+    g = lbm.Lattice(wl, storage="fp64")
+    g.step(_DUCT_STEPS)
+    _check_fp64_arrays(g, snap, kinds, "duct offset slugs")
+    g.close()
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("storage,bound", [("fp32_shift", 1e-4), ("fp16_shift_g", 1e-3)])
+def test_full_size_duct_reduced_precision(duct_oracle, storage, bound):
+    """The benchmark workload in the benchmarked storage modes: max |phi -
+    oracle| after 3 steps."""
+    wl, kinds, snap = duct_oracle
+    lbm = _lbm()
+    print("case duct %s steps %d" % (storage, _DUCT_STEPS), flush=True)
+    g = lbm.Lattice(wl, storage=storage)
+    g.step(_DUCT_STEPS)
+    dphi = float(np.abs(g.fields()[0] - snap["phi"])[kinds == 0].max())
+    g.close()
+    print(storage, "max |dphi|", dphi, flush=True)
+    assert dphi <= bound
