@@ -316,6 +316,29 @@ __device__ inline T wave_max(T v) {
 // ------------------------------------------------------------ node state
 // Per-node quantities the D3Q19 and D3Q7 updates need once the moments are
 // known (all in the compute precision T).
+// c_i . v over the non-zero components of c_i only (IEEE arithmetic keeps
+// 0 * v, so the zero components are left out explicitly; after unrolling
+// every test below is a compile-time constant)
+template <typename T> __device__ inline T cdot(int i, T v0, T v1, T v2) {
+    T r = T(0);
+    bool any = false;
+    if (CX[i]) { r = T(CX[i]) * v0; any = true; }
+    if (CY[i]) { r = any ? r + T(CY[i]) * v1 : T(CY[i]) * v1; any = true; }
+    if (CZ[i]) { r = any ? r + T(CZ[i]) * v2 : T(CZ[i]) * v2; }
+    return r;
+}
+// c_i c_i : Pi with Pi = (xx, yy, zz, xy, xz, yz), non-zero terms only
+template <typename T> __device__ inline T ccpi(int i, const T* P) {
+    T r = T(0);
+    if (CX[i]) r += P[0];
+    if (CY[i]) r += P[1];
+    if (CZ[i]) r += P[2];
+    if (CX[i] * CY[i]) r += T(2 * CX[i] * CY[i]) * P[3];
+    if (CX[i] * CZ[i]) r += T(2 * CX[i] * CZ[i]) * P[4];
+    if (CY[i] * CZ[i]) r += T(2 * CY[i] * CZ[i]) * P[5];
+    return r;
+}
+
 template <typename T> struct NodeState {
     T u[3], uu, grad[3], ug, V[3], uV, rho, pdev, Pi[6], trPi, om, pc, tn[3];
 };
@@ -329,16 +352,14 @@ template <typename T> struct NodeState {
 template <typename T, int MODE>
 __device__ inline T g_out(int i, const NodeState<T>& s, T rdif) {
     const T w = T(wg(i));
-    const T a = T(CX[i]) * s.u[0] + T(CY[i]) * s.u[1] + T(CZ[i]) * s.u[2];
+    const T a = cdot(i, s.u[0], s.u[1], s.u[2]);
     const T gam = T(3) * a + T(4.5) * a * a - T(1.5) * s.uu;
-    const T cgr = T(CX[i]) * s.grad[0] + T(CY[i]) * s.grad[1] + T(CZ[i]) * s.grad[2] - s.ug;
-    const T cv = T(CX[i]) * s.V[0] + T(CY[i]) * s.V[1] + T(CZ[i]) * s.V[2] - s.uV;
+    const T cgr = cdot(i, s.grad[0], s.grad[1], s.grad[2]) - s.ug;
+    const T cv = cdot(i, s.V[0], s.V[1], s.V[2]) - s.uV;
     const T K = w * (gam * rdif * cgr + (T(1) + gam) * cv);
     const T base = w * (s.rho * gam + s.pdev);
     if (MODE == MODE_INIT) return base - T(0.5) * K;
-    const T cPc = T(CX[i] * CX[i]) * s.Pi[0] + T(CY[i] * CY[i]) * s.Pi[1] + T(CZ[i] * CZ[i]) * s.Pi[2] +
-                  T(2 * CX[i] * CY[i]) * s.Pi[3] + T(2 * CX[i] * CZ[i]) * s.Pi[4] +
-                  T(2 * CY[i] * CZ[i]) * s.Pi[5];
+    const T cPc = ccpi(i, s.Pi);
     return base + T(0.5) * K + s.om * w * (cPc - s.trPi);
 }
 
@@ -346,11 +367,11 @@ __device__ inline T g_out(int i, const NodeState<T>& s, T rdif) {
 template <typename T, int MODE>
 __device__ inline void g_out_pair(int i, const NodeState<T>& s, T rdif, T& vp, T& vm) {
     const T w = T(wg(i));
-    const T a = T(CX[i]) * s.u[0] + T(CY[i]) * s.u[1] + T(CZ[i]) * s.u[2];
+    const T a = cdot(i, s.u[0], s.u[1], s.u[2]);
     const T e = T(4.5) * a * a - T(1.5) * s.uu;
     const T gp = e + T(3) * a, gm = e - T(3) * a;
-    const T b = T(CX[i]) * s.grad[0] + T(CY[i]) * s.grad[1] + T(CZ[i]) * s.grad[2];
-    const T c = T(CX[i]) * s.V[0] + T(CY[i]) * s.V[1] + T(CZ[i]) * s.V[2];
+    const T b = cdot(i, s.grad[0], s.grad[1], s.grad[2]);
+    const T c = cdot(i, s.V[0], s.V[1], s.V[2]);
     const T Kp = w * (gp * rdif * (b - s.ug) + (T(1) + gp) * (c - s.uV));
     const T Km = w * (gm * rdif * (-b - s.ug) + (T(1) + gm) * (-c - s.uV));
     const T bp = w * (s.rho * gp + s.pdev), bm = w * (s.rho * gm + s.pdev);
@@ -359,9 +380,7 @@ __device__ inline void g_out_pair(int i, const NodeState<T>& s, T rdif, T& vp, T
         vm = bm - T(0.5) * Km;
         return;
     }
-    const T cPc = T(CX[i] * CX[i]) * s.Pi[0] + T(CY[i] * CY[i]) * s.Pi[1] + T(CZ[i] * CZ[i]) * s.Pi[2] +
-                  T(2 * CX[i] * CY[i]) * s.Pi[3] + T(2 * CX[i] * CZ[i]) * s.Pi[4] +
-                  T(2 * CY[i] * CZ[i]) * s.Pi[5];
+    const T cPc = ccpi(i, s.Pi);
     const T filt = s.om * w * (cPc - s.trPi);
     vp = bp + T(0.5) * Kp + filt;
     vm = bm + T(0.5) * Km + filt;
@@ -372,9 +391,9 @@ __device__ inline void g_out_pair(int i, const NodeState<T>& s, T rdif, T& vp, T
 template <typename T>
 __device__ inline void h_eq_pair(int i, const NodeState<T>& s, T href, T& hp, T& hm) {
     const T w = T(wh(i));
-    const T a = T(CX[i]) * s.u[0] + T(CY[i]) * s.u[1] + T(CZ[i]) * s.u[2];
+    const T a = cdot(i, s.u[0], s.u[1], s.u[2]);
     const T e = (s.pc - href) + s.pc * (T(8) * a * a - T(2) * s.uu);
-    const T o = s.pc * T(4) * a + (T(CX[i]) * s.tn[0] + T(CY[i]) * s.tn[1] + T(CZ[i]) * s.tn[2]);
+    const T o = s.pc * T(4) * a + cdot(i, s.tn[0], s.tn[1], s.tn[2]);
     hp = w * (e + o);
     hm = w * (e - o);
 }
@@ -553,8 +572,7 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
                 const int sl = cz < 0 ? sm : (cz > 0 ? sp : s0);
                 const int mat = flag_sub(s_flag[sl][c0 + cy * LW + cx]);
                 const T ct = (T)D->cos_t[mat], sn = (T)D->sin_t[mat];
-                const T d = -ct * (nw[0] * T(cx) + nw[1] * T(cy) + nw[2] * T(cz)) +
-                            sn * (gt[0] * T(cx) + gt[1] * T(cy) + gt[2] * T(cz));
+                const T d = -ct * cdot(i, nw[0], nw[1], nw[2]) + sn * cdot(i, gt[0], gt[1], gt[2]);
                 const T t = dev_tanh(k2W * d);
                 // tanh(artanh(a) + 2d/W) by the addition theorem
                 return T(0.5) * (T(1) + (a + t) / (T(1) + a * t));
