@@ -55,7 +55,6 @@ constexpr double TGc = 1.0 / 3.0;  // D3Q19 lattice temperature
 constexpr double THc = 0.25;       // D3Q7 lattice temperature
 constexpr uint32_t SOLID_MASK = 0x7FFFEu;  // link bits 1..18
 
-constexpr int LDS_PLANE = 400;     // >= (TX + 2) * (TY + 2) for TX in {16, 32, 64}
 
 // ------------------------------------------------------ uniform values
 // Values read through the descriptor are the same for every lane of a
@@ -404,8 +403,12 @@ __device__ inline void h_eq_pair(int i, const NodeState<T>& s, T href, T& hp, T&
 template <typename T, typename SH, typename SG, int MODE, bool DIAG, int TX, int PAR>
 __global__ void __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(SWEEP_WAVES_PER_EU)))
 sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut ro, InitIn in) {
-    __shared__ T s_phi[4][LDS_PLANE];
-    __shared__ uint8_t s_flag[4][LDS_PLANE];
+    // LDS ring of phi and flags: each plane holds the tile plus a one-node
+    // halo, LN cells, staged NST cells per thread
+    constexpr int LW = TX + 2, LN = (TX + 2) * (NTHREADS / TX + 2);
+    constexpr int NST = (LN + NTHREADS - 1) / NTHREADS;
+    __shared__ T s_phi[4][LN];
+    __shared__ uint8_t s_flag[4][LN];
     __shared__ double s_red[NPART][NTHREADS / 64];
     __shared__ int s_last;
 
@@ -435,31 +438,24 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
     const T iTg = T(3), i2Tg2 = T(4.5);
     const T rdif = ph[PI_RDIF];
 
-    // LDS ring of phi and flags: each plane holds the tile plus a one-node
-    // halo; a thread stages at most two cells, whose in-plane offsets (with
-    // the periodic wrap) are fixed for the whole z-march
-    constexpr int LW = TX + 2, LN = (TX + 2) * (TY + 2);
-    static_assert(LN <= LDS_PLANE && LN <= 2 * NTHREADS, "LDS plane");
-    int coff0, coff1 = -1;
-    {
-        const int lx = tid % LW, ly = tid / LW;
-        coff0 = wrapc(tl.x0 - 1 + lx, nx) + nx * wrapc(tl.y0 - 1 + ly, ny);
-        const int c1 = tid + NTHREADS;
-        if (c1 < LN) {
-            const int lx1 = c1 % LW, ly1 = c1 / LW;
-            coff1 = wrapc(tl.x0 - 1 + lx1, nx) + nx * wrapc(tl.y0 - 1 + ly1, ny);
-        }
+    // a thread stages cells tid + j * NTHREADS; their in-plane offsets (with
+    // the periodic wrap) are fixed for the whole z-march (-1: no cell)
+    static_assert(TY + 2 <= NTHREADS, "LDS plane");
+    int coff[NST];
+#pragma unroll
+    for (int j = 0; j < NST; ++j) {
+        const int c = tid + j * NTHREADS;
+        coff[j] = -1;
+        if (c < LN) coff[j] = wrapc(tl.x0 - 1 + c % LW, nx) + nx * wrapc(tl.y0 - 1 + c / LW, ny);
     }
     auto stage = [&](int m, int zp) {
         const int zz = zp < 0 ? zp + nz : (zp >= nz ? zp - nz : zp);
         const int zo = zz * nxy;
-        if (tid < LN) {
-            s_phi[m & 3][tid] = phig[coff0 + zo];
-            s_flag[m & 3][tid] = flg[coff0 + zo];
-        }
-        if (coff1 >= 0) {
-            s_phi[m & 3][tid + NTHREADS] = phig[coff1 + zo];
-            s_flag[m & 3][tid + NTHREADS] = flg[coff1 + zo];
+#pragma unroll
+        for (int j = 0; j < NST; ++j) {
+            if (coff[j] < 0) continue;
+            s_phi[m & 3][tid + j * NTHREADS] = phig[coff[j] + zo];
+            s_flag[m & 3][tid + j * NTHREADS] = flg[coff[j] + zo];
         }
     };
 
@@ -481,13 +477,14 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
     for (int k = 0; k < tl.zn; ++k) {
         const int z = tl.z0 + k;
         const bool more = k + 1 < tl.zn;
-        T nv0 = T(0), nv1 = T(0);
-        uint8_t nf0 = 0, nf1 = 0;
+        T nv[NST];
+        uint8_t nf[NST];
         if (more) {
             const int zq = z + 2 >= nz ? z + 2 - nz : z + 2;
             const int zo = zq * nxy;
-            if (tid < LN) { nv0 = phig[coff0 + zo]; nf0 = flg[coff0 + zo]; }
-            if (coff1 >= 0) { nv1 = phig[coff1 + zo]; nf1 = flg[coff1 + zo]; }
+#pragma unroll
+            for (int j = 0; j < NST; ++j)
+                if (coff[j] >= 0) { nv[j] = phig[coff[j] + zo]; nf[j] = flg[coff[j] + zo]; }
         }
         do {
         if (!active) continue;
@@ -819,8 +816,9 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
         } while (0);
         if (more) {
             const int m = (k + 3) & 3;
-            if (tid < LN) { s_phi[m][tid] = nv0; s_flag[m][tid] = nf0; }
-            if (coff1 >= 0) { s_phi[m][tid + NTHREADS] = nv1; s_flag[m][tid + NTHREADS] = nf1; }
+#pragma unroll
+            for (int j = 0; j < NST; ++j)
+                if (coff[j] >= 0) { s_phi[m][tid + j * NTHREADS] = nv[j]; s_flag[m][tid + j * NTHREADS] = nf[j]; }
         }
         __syncthreads();
     }

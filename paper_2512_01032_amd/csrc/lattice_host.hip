@@ -95,6 +95,7 @@ int validate_params(const lbm_params* p, const lbm_geometry* geo) {
 }
 
 int choose_tx(int nx) {
+    // fewest idle lanes on the ragged x end; among equals the widest tile
     int best = 64, waste_best = 1 << 30;
     for (int tx : {64, 32, 16}) {
         const int waste = ((nx + tx - 1) / tx) * tx - nx;
