@@ -77,7 +77,8 @@ class BruteForce:
         u = np.zeros((3,) + shape) if wl.u0 is None else wl.u0.copy()
         u = u * self.fluid
         P = np.full(shape, ph.P_ref) if wl.P0 is None else wl.P0.copy()
-        grad, lap = self._stencil(phi)
+        self.hist = np.zeros((19,) + shape)     # wall values of the last step (hysteresis)
+        grad, lap = self._stencil(phi, "set")
         heq = self._heq(phi, u, grad, lap)
         geq, K = self._geq(phi, u, P, grad, lap)
         self.h = heq * self.fluid
@@ -123,7 +124,10 @@ class BruteForce:
         uu = (u ** 2).sum(0)
         return w * (1 + cu / T + cu ** 2 / (2 * T * T) - uu / (2 * T))
 
-    def _stencil(self, phi):
+    def _stencil(self, phi, hist_mode="eval"):
+        """hist_mode (hysteresis only): "set" records the wall values,
+        "step" blends them with the recorded ones and records the result,
+        "eval" blends without recording."""
         ph = self.ph
         nb = np.zeros((19,) + self.shape)
         sol = np.zeros((19,) + self.shape, bool)
@@ -151,6 +155,13 @@ class BruteForce:
             w = -np.cos(th) * nw + np.sin(th) * that
             d = w[0] * C[i][0] + w[1] * C[i][1] + w[2] * C[i][2]
             ps = 0.5 * (1 + np.tanh((x_x0 + d) / (0.5 * ph.W)))
+            if getattr(ph, "hysteresis", False):
+                if hist_mode == "set":
+                    self.hist[i] = np.where(sol[i], ps, self.hist[i])
+                else:
+                    ps = ph.hyst_beta * self.hist[i] + (1 - ph.hyst_beta) * ps
+                    if hist_mode == "step":
+                        self.hist[i] = np.where(sol[i], ps, self.hist[i])
             nb[i] = np.where(sol[i], ps, nb[i])
         grad = np.zeros((3,) + self.shape)
         lap = np.zeros(self.shape)
@@ -230,7 +241,7 @@ class BruteForce:
         phi = np.where(self.fluid, self.h.sum(0), 0.0)
         phi = self._ghost_copy(phi)
         self.phi = phi
-        grad, lap = self._stencil(phi)
+        grad, lap = self._stencil(phi, "step")
         u, P = self._moments(phi, grad, lap)
         u = u * self.fluid
         self.u = u

@@ -62,6 +62,7 @@ struct lbmref_state {
     int8_t *gface;   /* face of a ghost node */
     long *owner;     /* interior node one step inward from a ghost */
     double *nw;      /* [N*3] unit wall normal into the fluid, 0 without solid links */
+    double *hyst;    /* [N*19] wall value each link used last (hysteresis), or NULL */
     double *h[2];    /* [N*7]  population i of node n at n*7+i */
     double *g[2];    /* [N*19] */
     int cur;
@@ -237,7 +238,12 @@ double lbmref_wet_phi_s(double phi_smpl, const double w[3], const int c[3], doub
 
 /* S2 + S3 at fluid node n: gradient and Laplacian of phi with the wetting
  * substitute at solid links. */
-static void stencil(const lbmref_state *s, long n, double grad[3], double *lap) {
+/* What stencil() does with the hysteresis history of a node's wall links:
+ * EVAL blends with it (read-out), STEP blends and stores the blended value
+ * (a time step), SET stores the unblended value (initial state, restore). */
+enum { HYST_EVAL = 0, HYST_STEP = 1, HYST_SET = 2 };
+
+static void stencil(lbmref_state *s, long n, double grad[3], double *lap, int hmode) {
     const lbmref_params *p = &s->p;
     double pc = s->phi[n];
     double ph[19];
@@ -263,6 +269,15 @@ static void stencil(const lbmref_state *s, long n, double grad[3], double *lap) 
             double w[3];
             lbmref_wet_direction(nw, g0, p->theta_deg[s->mat[m]], p->eps, w);
             ph[i] = lbmref_wet_phi_s(pc, w, CV[i], p->W, p->clamp_a);
+            if (p->hysteresis) {
+                double *prev = &s->hyst[19 * n + i];
+                if (hmode == HYST_SET) {
+                    *prev = ph[i];
+                } else {
+                    ph[i] = p->hyst_beta * (*prev) + (1.0 - p->hyst_beta) * ph[i];
+                    if (hmode == HYST_STEP) *prev = ph[i];
+                }
+            }
         }
     }
     /* Eq. 16 as printed: gradient from the differences phi(x + c_i) - phi(x - c_i)
@@ -400,7 +415,7 @@ static void macroscopic(lbmref_state *s) {
     for (long n = 0; n < s->N; ++n) {
         if (s->kind[n] != K_FLUID) continue;
         double grad[3], lap, u[3], P;
-        stencil(s, n, grad, &lap);
+        stencil(s, n, grad, &lap, HYST_EVAL);
         hydro_moments(p, &g[19 * n], s->phi[n], grad, lap, u, &P);
         for (int a = 0; a < 3; ++a) {
             s->u[3 * n + a] = u[a];
@@ -428,6 +443,7 @@ lbmref_state *lbmref_create(const lbmref_params *p, const uint8_t *solid,
     s->kind = malloc(N); s->mat = malloc(N); s->gface = malloc(N);
     s->owner = malloc(N * sizeof(long));
     s->nw = malloc(3 * N * sizeof(double));
+    s->hyst = p->hysteresis ? calloc(19 * N, sizeof(double)) : NULL;
     for (int k = 0; k < 2; ++k) {
         s->h[k] = calloc(7 * N, sizeof(double));
         s->g[k] = calloc(19 * N, sizeof(double));
@@ -436,7 +452,8 @@ lbmref_state *lbmref_create(const lbmref_params *p, const uint8_t *solid,
     s->u = calloc(3 * N, sizeof(double)); s->P = calloc(N, sizeof(double));
     s->grad = calloc(3 * N, sizeof(double)); s->lap = calloc(N, sizeof(double));
     s->mu = calloc(N, sizeof(double));
-    if (!s->kind || !s->mat || !s->gface || !s->owner || !s->nw || !s->h[0] || !s->h[1] ||
+    if (!s->kind || !s->mat || !s->gface || !s->owner || !s->nw || (p->hysteresis && !s->hyst) ||
+        !s->h[0] || !s->h[1] ||
         !s->g[0] || !s->g[1] || !s->phi || !s->rho || !s->u || !s->P || !s->grad ||
         !s->lap || !s->mu) {
         lbmref_destroy(s);
@@ -455,7 +472,7 @@ lbmref_state *lbmref_create(const lbmref_params *p, const uint8_t *solid,
     for (long n = 0; n < N; ++n) {
         if (s->kind[n] != K_FLUID) continue;
         double grad[3], lap, u[3], P;
-        stencil(s, n, grad, &lap);
+        stencil(s, n, grad, &lap, HYST_SET);
         for (int a = 0; a < 3; ++a) u[a] = u0 ? u0[a * N + n] : 0.0;
         P = P0 ? P0[n] : p->P_ref;
         double heq[7], geq[19], K[19];
@@ -472,7 +489,7 @@ lbmref_state *lbmref_create(const lbmref_params *p, const uint8_t *solid,
 
 void lbmref_destroy(lbmref_state *s) {
     if (!s) return;
-    free(s->kind); free(s->mat); free(s->gface); free(s->owner); free(s->nw);
+    free(s->kind); free(s->mat); free(s->gface); free(s->owner); free(s->nw); free(s->hyst);
     for (int k = 0; k < 2; ++k) { free(s->h[k]); free(s->g[k]); }
     free(s->phi); free(s->rho); free(s->u); free(s->P); free(s->grad); free(s->lap);
     free(s->mu);
@@ -494,7 +511,7 @@ static void one_step(lbmref_state *s) {
     for (long n = 0; n < N; ++n) {
         if (s->kind[n] != K_FLUID) continue;
         double grad[3], lap, u[3], P, gout[19], heq[7];
-        stencil(s, n, grad, &lap);
+        stencil(s, n, grad, &lap, HYST_STEP);
         double ph = s->phi[n];
         lbmref_collide_g_node(p, &gA[19 * n], ph, grad, lap, gout, u, &P);
         heq_node(p, ph, u, grad, lap, heq);
@@ -588,6 +605,15 @@ void lbmref_set_pops(lbmref_state *s, const double *h, const double *g, long ste
         for (int i = 0; i < 19; ++i) gA[19 * n + i] = g[i * N + n];
     }
     s->step = step;
+    if (s->p.hysteresis) {
+        /* the history of the wall values restarts from the restored state */
+        phase_moment(s);
+        for (long n = 0; n < N; ++n) {
+            if (s->kind[n] != K_FLUID) continue;
+            double grad[3], lap;
+            stencil(s, n, grad, &lap, HYST_SET);
+        }
+    }
 }
 
 void lbmref_diagnostics(lbmref_state *s, lbmref_diag *d) {

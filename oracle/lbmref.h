@@ -53,6 +53,11 @@ typedef struct lbmref_params {
     double face_P[6], face_ramp[6];
     double theta_deg[16];  /* contact angle per solid material */
     double clamp_a;        /* a = 2 phi - 1 is clamped to [-1+clamp_a, 1-clamp_a] */
+    /* contact-angle hysteresis (Sec. III.A): each wall link blends its value
+     * phi_s,i with the one it used at the previous step,
+     * phi_s,i = beta * previous + (1 - beta) * phi_s,i (current gradient) */
+    int hysteresis;
+    double hyst_beta;
 } lbmref_params;
 
 typedef struct lbmref_diag {

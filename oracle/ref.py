@@ -49,6 +49,7 @@ class Params(ctypes.Structure):
         ("face_ramp", ctypes.c_double * 6),
         ("theta_deg", ctypes.c_double * 16),
         ("clamp_a", ctypes.c_double),
+        ("hysteresis", ctypes.c_int), ("hyst_beta", ctypes.c_double),
     ]
 
 
@@ -122,6 +123,8 @@ def make_params(wl, clamp_a=1e-12):
     for k in range(16):
         p.theta_deg[k] = wl.theta_deg[k]
     p.clamp_a = clamp_a
+    p.hysteresis = int(getattr(ph, "hysteresis", False))
+    p.hyst_beta = getattr(ph, "hyst_beta", 0.0)
     return p
 
 

@@ -57,11 +57,15 @@ class Physics:
     slip_lo: float = 0.5
     slip_hi: float = 0.95
     P_ref: float = T_G
+    hysteresis: bool = False        # Sec. III.A: wall values blended with the previous step's
+    hyst_beta: float = 0.95
 
 
-def optimised(ph: Physics) -> Physics:
-    """The Sec. III.A model: tanh mixture switch and free slip in the band."""
-    return dataclasses.replace(ph, mix_tanh=True, interface_slip=True)
+def optimised(ph: Physics, hysteresis: bool = False) -> Physics:
+    """The Sec. III.A model: tanh mixture switch and free slip in the band;
+    with hysteresis=True also the blend of each wall value with the one of
+    the previous step (factor hyst_beta)."""
+    return dataclasses.replace(ph, mix_tanh=True, interface_slip=True, hysteresis=hysteresis)
 
 
 @dataclasses.dataclass

@@ -6,6 +6,7 @@ Runs on the CPU only.
 """
 from __future__ import annotations
 
+import dataclasses
 import math
 import os
 
@@ -24,13 +25,18 @@ def relmax(a, b):
 
 
 # --------------------------------------------------------------------- P1
-@pytest.mark.parametrize("kw", [dict(), dict(walls=True), dict(walls=True, open_x=True),
-                                dict(walls=True, open_x=True, optimised_model=True)])
-def test_bruteforce_reference_agrees(kw):
+@pytest.mark.parametrize("kw,hyst", [(dict(), False), (dict(walls=True), False),
+                                     (dict(walls=True, open_x=True), False),
+                                     (dict(walls=True, open_x=True, optimised_model=True), False),
+                                     (dict(walls=True, open_x=True, optimised_model=True), True)])
+def test_bruteforce_reference_agrees(kw, hyst):
     """Whole-lattice NumPy transcription (np.roll streaming, masks) vs the
     node-by-node C oracle on a tiny lattice: pins indexing, periodic wrap,
-    bounce-back, wall normals and ghost bookkeeping."""
+    bounce-back, wall normals and ghost bookkeeping, and (hyst) the history
+    of the wall values, whose first blend only shows from the second step."""
     wl = I.random_small(8, 6, 7, seed=3, **kw)
+    if hyst:
+        wl.phys = dataclasses.replace(wl.phys, hysteresis=True, hyst_beta=0.95)
     o = ref.Oracle(wl)
     b = bruteforce.BruteForce(wl)
     o.step(6)
@@ -358,6 +364,56 @@ def test_neutral_wetting_continues_a_perpendicular_interface():
     wl2 = I.Workload("perp60", nx, 1, nz, I.Physics(W=W), phi0, solid=solid, theta_deg=tuple(th))
     h2, g2 = ref.Oracle(wl2).pops()
     assert np.abs(h2[:, 1, :, cols] - h2[:, mid, :, cols]).max() >= 1e-4 * np.abs(h2).max()
+
+
+# ------------------------------------------------- contact-angle hysteresis
+def _cap_contact_line(phi_xz):
+    """x of the phi = 0.5 crossings on the first fluid row above the wall."""
+    return measure.crossings_1d(phi_xz[1])
+
+
+def test_hysteresis_with_zero_blend_is_no_hysteresis():
+    """beta = 0 keeps no history (the blend returns the current value
+    exactly): identical to the model without hysteresis, bitwise."""
+    wl = I.random_small(10, 8, 9, seed=4, walls=True, open_x=True, optimised_model=True)
+    a = ref.Oracle(wl)
+    wl0 = I.random_small(10, 8, 9, seed=4, walls=True, open_x=True, optimised_model=True)
+    wl0.phys = dataclasses.replace(wl0.phys, hysteresis=True, hyst_beta=0.0)
+    b = ref.Oracle(wl0)
+    a.step(12)
+    b.step(12)
+    ha, ga = a.pops()
+    hb, gb = b.pops()
+    assert np.array_equal(ha, hb) and np.array_equal(ga, gb)
+
+
+def test_hysteresis_delays_the_contact_line_but_not_the_angle():
+    """A cap started at 90 degrees on a 60 degree wall.  With the blend (beta
+    = 0.95, a memory of ~1/(1 - beta) = 20 steps) the wall values follow the
+    gradient with a lag, so after 40 steps the contact line has moved less
+    than without it (measured: 0.90 of the distance), but not frozen; the
+    equilibrium angle is the same (the blend's fixed point is the unblended
+    value).  Swapping the factors (a 0.05-step memory) or never updating the
+    history fails one of the bounds."""
+    out = {}
+    for hyst in (False, True):
+        wl = I.wall_cap_2d(60.0)
+        wl.phys = dataclasses.replace(wl.phys, hysteresis=hyst, hyst_beta=0.95)
+        o = ref.Oracle(wl)
+        x0 = _cap_contact_line(o.fields()[0][:, 0, :])[0]
+        o.step(40)
+        x1 = _cap_contact_line(o.fields()[0][:, 0, :])[0]
+        o.step(7960)
+        phi = o.fields()[0][:, 0, :]
+        pts = measure.contour_points_xz(phi, z_min=1)
+        pts = pts[pts[:, 1] > 2.5]
+        xc, zc, Rf = measure.fit_circle(pts)
+        out[hyst] = (abs(x1 - x0), theory.cap_angle_from_circle(zc, Rf, 0.5))
+    moved_plain, angle_plain = out[False]
+    moved_hyst, angle_hyst = out[True]
+    assert moved_plain > 0.1
+    assert 0.5 * moved_plain <= moved_hyst <= 0.95 * moved_plain
+    assert abs(angle_hyst - angle_plain) <= 0.2
 
 
 # -------------------------------------------------------------------- P10
