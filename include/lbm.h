@@ -90,6 +90,12 @@ typedef struct lbm_params {
     double u_max;           /* stability limit on |u| (<= 0: NaN check only) */
     int32_t fp16_log2_scale_h; /* FP16 storage scale 2^k of h deviations (0: default) */
     int32_t fp16_log2_scale_g; /* FP16 storage scale 2^k of g deviations (0: default) */
+    int32_t hysteresis;     /* 1: contact-angle hysteresis of the optimised model (Sec. III.A):
+                               each wall link uses hyst_beta * (its value of the previous
+                               step) + (1 - hyst_beta) * (the value from the current
+                               gradient) and keeps the result; the history starts from the
+                               current values at creation and after a restore */
+    double hyst_beta;       /* blend factor in [0, 1) (the paper's 0.95) */
 } lbm_params;
 
 /* Voxel geometry.  solid[n] = 0: fluid; 1 + k: solid of material k (< 16).
@@ -144,7 +150,10 @@ typedef struct lbm_diag {
 typedef struct lbm_handle lbm_handle;
 
 /* Bytes of device memory one lattice needs (populations, phi, flags, tile
- * table and reduction partials).  0 if the parameters are invalid. */
+ * table and reduction partials).  0 if the parameters are invalid.  With
+ * hysteresis the wall-value history is sized as if every node had wall links
+ * (the geometry is not known here): an upper bound; lbm_create allocates the
+ * exact amount when it allocates itself. */
 size_t lbm_footprint(const lbm_params *p);
 
 /* Validate, allocate (or carve the arena), upload geometry and initial state

@@ -53,7 +53,6 @@ __host__ __device__ constexpr double wg(int i) { return i == 0 ? 1.0 / 3.0 : (i 
 __host__ __device__ constexpr double wh(int i) { return i == 0 ? 0.25 : 0.125; }
 constexpr double TGc = 1.0 / 3.0;  // D3Q19 lattice temperature
 constexpr double THc = 0.25;       // D3Q7 lattice temperature
-constexpr uint32_t SOLID_MASK = 0x7FFFEu;  // link bits 1..18
 
 
 // ------------------------------------------------------ uniform values
@@ -564,6 +563,19 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
             a = a > T(1) - ph[PI_CLAMP_A] ? T(1) - ph[PI_CLAMP_A] : a;
             a = a < -T(1) + ph[PI_CLAMP_A] ? -T(1) + ph[PI_CLAMP_A] : a;
             const T k2W = ph[PI_K2W];
+            // contact-angle hysteresis (Sec. III.A): the wall value of link i
+            // is blended with the one this node used at the previous step
+            // (history slot wslot[n], [18][n_wall] layout); initialisation and
+            // a reset pass record the current values
+            const bool hyst = uni(D->hysteresis) != 0;
+            T* __restrict__ hist = nullptr;
+            int64_t hslot = 0, hstride = 0;
+            if (hyst) {
+                hist = unip((T*)D->hyst);
+                hstride = uni(D->n_wall);
+                hslot = D->wslot[n];
+            }
+            const bool record = MODE == MODE_INIT || (MODE == MODE_READ && uni(D->hyst_reset) != 0);
             auto phis = [&](int i) -> T {
                 const int cx = CX[i], cy = CY[i], cz = CZ[i];
                 const int sl = cz < 0 ? sm : (cz > 0 ? sp : s0);
@@ -572,7 +584,17 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
                 const T d = -ct * cdot(i, nw[0], nw[1], nw[2]) + sn * cdot(i, gt[0], gt[1], gt[2]);
                 const T t = dev_tanh(k2W * d);
                 // tanh(artanh(a) + 2d/W) by the addition theorem
-                return T(0.5) * (T(1) + (a + t) / (T(1) + a * t));
+                T ps = T(0.5) * (T(1) + (a + t) / (T(1) + a * t));
+                if (hyst) {
+                    T* hp = hist + (int64_t)(i - 1) * hstride + hslot;
+                    if (record) {
+                        *hp = ps;
+                    } else {
+                        ps = ph[PI_HBETA] * *hp + ph[PI_HBETA1] * ps;
+                        if (MODE == MODE_STEP) *hp = ps;
+                    }
+                }
+                return ps;
             };
             gx = gy = gz = lap = T(0);
             for (int i = 1; i < 19; i += 2) {

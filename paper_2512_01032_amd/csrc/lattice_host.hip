@@ -63,6 +63,10 @@ int validate_params(const lbm_params* p, const lbm_geometry* geo) {
             return LBM_E_INVAL;
         }
     }
+    if (p->hysteresis && !(p->hyst_beta >= 0.0 && p->hyst_beta < 1.0)) {
+        set_error("hyst_beta %g outside [0, 1)", p->hyst_beta);
+        return LBM_E_INVAL;
+    }
     if (!(p->rho_l > 0) || !(p->rho_g > 0)) { set_error("densities must be > 0"); return LBM_E_INVAL; }
     if (!(p->nu_l > 0) || !(p->nu_g > 0)) { set_error("viscosities must be > 0 (tau > 1/2)"); return LBM_E_INVAL; }
     if (!(p->W > 0)) { set_error("interface width W must be > 0"); return LBM_E_INVAL; }
@@ -148,6 +152,9 @@ static void layout_offsets(const lbm_params* p, int64_t ntiles, int64_t nghosts,
     L->off_partials = o; o = align256(o + (size_t)ntiles * NPART * sizeof(double));
     L->off_gbuf = o; o = align256(o + (size_t)3 * L->gface_count * sphi);
     L->off_ghosts = o; o = align256(o + (size_t)nghosts * sizeof(GhostRef));
+    // hysteresis: per-node history slot, 18 wall values per near-wall node
+    L->off_wslot = o; if (p->hysteresis) o = align256(o + (size_t)N * 4);
+    L->off_hyst = o; if (p->hysteresis) o = align256(o + (size_t)(QG - 1) * L->n_wall * sphi);
     L->total = o;
 }
 
@@ -159,6 +166,7 @@ size_t footprint_bytes(const lbm_params* p) {
     const int64_t ntiles = (int64_t)((p->nx + tx - 1) / tx) * ((p->ny + ty - 1) / ty) *
                            ((p->nz + tz - 1) / tz);
     face_planes(p, &L);
+    L.n_wall = L.N;                                  // bound: every node near a wall
     layout_offsets(p, ntiles, L.gface_count, &L);   // ghosts <= face entries
     return L.total;
 }
@@ -238,6 +246,16 @@ int build_layout(const lbm_params* p, const lbm_geometry* geo, int lat, LatticeL
             }
         }
     }
+    // history slots of the wall values, in node order (coalesced along x)
+    L->n_wall = 0;
+    if (p->hysteresis) {
+        L->wslot.assign(N, -1);
+        for (int64_t n = 0; n < N; ++n)
+            if ((L->link[n] & SOLID_MASK) && flag_kind(L->flag[n]) == KIND_FLUID)
+                L->wslot[n] = (int32_t)L->n_wall++;
+    } else {
+        std::vector<int32_t>().swap(L->wslot);
+    }
     // tile table: keep tiles holding at least one non-solid node
     const int tx = choose_tx(nx), ty = NTHREADS / tx, tz = choose_tz(p, tx);
     L->tx = tx; L->ty = ty; L->tz = tz;
@@ -282,6 +300,11 @@ void fill_desc(const lbm_params* p, const lbm_geometry* geo, const LatticeLayout
     d->link = (const uint32_t*)(base + L.off_link);
     d->partials = (double*)(base + L.off_partials);
     d->gbuf = base + L.off_gbuf;
+    d->hysteresis = p->hysteresis ? 1 : 0;
+    d->hyst_reset = 0;
+    d->n_wall = p->hysteresis ? L.n_wall : 0;
+    d->wslot = p->hysteresis ? (const int32_t*)(base + L.off_wslot) : nullptr;
+    d->hyst = p->hysteresis ? (void*)(base + L.off_hyst) : nullptr;
     for (int f = 0; f < 6; ++f) d->gface_base[f] = L.gface_base[f];
     d->gface_count = L.gface_count;
     d->counter = (unsigned int*)(base + L.off_counter);
@@ -352,6 +375,8 @@ void fill_desc(const lbm_params* p, const lbm_geometry* geo, const LatticeLayout
     v[PI_FZ] = p->F_ex[2];
     v[PI_K2W] = 2.0 / p->W;
     v[PI_PREF_DEV] = p->P_ref / TG - d->gref;
+    v[PI_HBETA] = p->hysteresis ? p->hyst_beta : 0.0;
+    v[PI_HBETA1] = 1.0 - v[PI_HBETA];
     for (int k = 0; k < PI_COUNT; ++k) {
         d->pd[k] = v[k];
         d->pf[k] = (float)v[k];
@@ -379,6 +404,8 @@ int upload_and_init(const lbm_params* p, const lbm_geometry* geo, const lbm_init
     HIPCHK(hipMemsetAsync(base + L.off_partials, 0, L.tiles.size() * NPART * sizeof(double), s));
     HIPCHK(hipMemcpyAsync(base + L.off_flag, L.flag.data(), N, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(base + L.off_link, L.link.data(), (size_t)N * 4, hipMemcpyHostToDevice, s));
+    if (p->hysteresis)
+        HIPCHK(hipMemcpyAsync(base + L.off_wslot, L.wslot.data(), (size_t)N * 4, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(base + L.off_tiles, L.tiles.data(), L.tiles.size() * sizeof(Tile),
                           hipMemcpyHostToDevice, s));
     if (!L.ghosts.empty())
@@ -403,6 +430,18 @@ int upload_and_init(const lbm_params* p, const lbm_geometry* geo, const lbm_init
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         hipFree(dpops);
         if (e != hipSuccess) { set_error("restore: %s", hipGetErrorString(e)); return LBM_E_DEVICE; }
+        if (p->hysteresis) {
+            // the wall-value history restarts from the restored state: a read
+            // pass with hyst_reset set records the current wall values
+            const int32_t on = 1, off = 0;
+            HIPCHK(hipMemcpyAsync(&ddesc->hyst_reset, &on, sizeof(on), hipMemcpyHostToDevice, s));
+            HIPCHK(hipStreamSynchronize(s));
+            int rc = read_lattice(p->storage, *hdesc, (int)(step0 & 1), ddesc, dtiles, nt, 0, nullptr,
+                                  nullptr, nullptr, nullptr, s);
+            HIPCHK(hipMemcpyAsync(&ddesc->hyst_reset, &off, sizeof(off), hipMemcpyHostToDevice, s));
+            HIPCHK(hipStreamSynchronize(s));
+            if (rc != LBM_OK) return rc;
+        }
         return LBM_OK;
     }
     if (init->kind != LBM_INIT_FIELDS || !init->phi) {

@@ -39,6 +39,8 @@ constexpr int LINK_OWNER_SHIFT = 24;
 // storage modes (same values as enum lbm_storage)
 constexpr int ST_FP64 = 0, ST_FP32 = 1, ST_FP32_SHIFT = 2, ST_FP16_G = 3, ST_FP16_ALL = 4;
 
+constexpr uint32_t SOLID_MASK = 0x7FFFEu;  // link bits 1..18
+
 struct alignas(16) Tile {
     int32_t lat;      // lattice index in the descriptor array
     int32_t x0, y0;   // first column of the tile
@@ -66,8 +68,13 @@ struct alignas(256) Desc {
     void* gbuf;                    // [3][face entries] u of each ghost's owner (compute type)
     int64_t gface_base[6];         // first entry of each face plane in gbuf
     int64_t gface_count;           // entries per velocity component
+    void* hyst;                    // [18][n_wall] wall values of the last step (compute type)
+    const int32_t* wslot;          // [N] slot of a near-wall fluid node in hyst
+    int64_t n_wall;                // near-wall fluid nodes (hysteresis only, else 0)
+    int32_t hysteresis;            // 1: wall values blended with their history
+    int32_t hyst_reset;            // a read pass records the current wall values instead
     // time
-    int64_t step;                  // advanced on the device by the last tile of a sweep
+    int64_t step;                  // advanced on the device after each step's ghost pass
     int64_t t0;                    // step counter value at physical time 0
     int64_t stop_step;             // the sweep leaves the lattice alone from here on
     int64_t diag_every;            // 0: never
@@ -101,8 +108,9 @@ enum ParamIndex {
     PI_RHO_G = 0, PI_RDIF, PI_MU3, PI_MULAP, PI_TAU_G, PI_TAU_L, PI_THETA0, PI_MC_K, PI_MC_INVD,
     PI_MC_PHI_M, PI_MC_PHI_m, PI_EPS, PI_MIX_PHI, PI_MIX_INVW, PI_SLIP_LO, PI_SLIP_HI, PI_CLAMP_A,
     PI_HREF, PI_GREF, PI_SH, PI_SG, PI_INV_SH, PI_INV_SG, PI_ITAU_H, PI_FX, PI_FY, PI_FZ,
-    PI_K2W, PI_PREF_DEV, PI_COUNT
+    PI_K2W, PI_PREF_DEV, PI_HBETA, PI_HBETA1, PI_COUNT
 };
+static_assert(PI_COUNT <= 32, "parameter block");
 
 // diagnostic partial slots
 enum { P_PHI = 0, P_MX, P_MY, P_MZ, P_UMAX, P_NAN, P_PLIQ, P_NLIQ, P_PGAS, P_NGAS };

@@ -42,6 +42,7 @@ class lbm_params(ctypes.Structure):
         ("face_bc", c_int32 * 6), ("face_P", c_double * 6), ("face_ramp", c_double * 6),
         ("diag_every", c_int32), ("u_max", c_double),
         ("fp16_log2_scale_h", c_int32), ("fp16_log2_scale_g", c_int32),
+        ("hysteresis", c_int32), ("hyst_beta", c_double),
     ]
 
 
@@ -186,6 +187,8 @@ def params_from_workload(wl, storage=None, diag_every=0, u_max=0.0):
         p.face_ramp[f] = 0.0 if fc is None else fc[1]
     p.diag_every = int(diag_every)
     p.u_max = float(u_max)
+    p.hysteresis = 1 if getattr(ph, "hysteresis", False) else 0
+    p.hyst_beta = float(getattr(ph, "hyst_beta", 0.0))
     return p
 
 

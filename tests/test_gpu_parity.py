@@ -329,3 +329,51 @@ def test_full_size_duct_reduced_precision(duct_oracle, storage, bound):
     g.close()
     print(storage, "max |dphi|", dphi, flush=True)
     assert dphi <= bound
+
+
+# ------------------------------------------------- contact-angle hysteresis
+def _hyst_workload(seed=8):
+    import dataclasses
+    from paper_2512_01032_amd import inputs
+    wl = inputs.random_small(40, 12, 10, seed=seed, walls=True, open_x=True,
+                             optimised_model=True, u_amp=0.002)
+    wl.phys = dataclasses.replace(wl.phys, hysteresis=True, hyst_beta=0.95)
+    return wl
+
+
+def test_hysteresis_fp64():
+    """Wall values blended with their history (Sec. III.A), walls and
+    pressure faces, FP64: 1e-10 after 30 steps."""
+    g, o = _run_pair(_hyst_workload(), 30)
+    err = compare_state(g, o, o.kinds())
+    print(err, flush=True)
+    for k in STRICT:
+        assert err[k] <= FP64_TOL, (k, err[k])
+
+
+def test_hysteresis_restore_fp64():
+    """Restoring populations restarts the wall-value history from the
+    restored state on both sides: GPU and oracle, both restored at step 13,
+    agree to 1e-10 after 12 more steps."""
+    from oracle import ref
+    lbm = _lbm()
+    wl = _hyst_workload(seed=9)
+    a = lbm.Lattice(wl, storage="fp64")
+    a.step(13)
+    h, gp = a.pops()
+    b = lbm.Lattice(wl, storage="fp64", pops=np.concatenate([h, gp]), step=13)
+    b.step(12)
+    o = ref.Oracle(wl)
+    o.set_pops(h, gp, 13)
+    o.step(12)
+    err = compare_state(b, o, o.kinds())
+    print(err, flush=True)
+    for k in STRICT:
+        assert err[k] <= FP64_TOL, (k, err[k])
+
+
+def test_hysteresis_fp32_shift():
+    g, o = _run_pair(_hyst_workload(), 50, "fp32_shift")
+    err = compare_state(g, o, o.kinds())
+    print(err, flush=True)
+    assert err["phi"] <= 1e-5, err
