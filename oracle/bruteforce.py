@@ -104,6 +104,12 @@ class BruteForce:
     def _ghost_copy(self, phi):
         return np.where(self.ghost, self._owner_value(phi), phi)
 
+    def _phase_lattice(self):
+        """Size, weights and temperature of the phase-field lattice."""
+        if getattr(self.ph, "q_phase", 7) == 19:
+            return 19, WG, TG
+        return 7, WH, TH
+
     def _rho(self, phi):
         ph = self.ph
         return ph.rho_g + np.clip(phi, 0, 1) * (ph.rho_l - ph.rho_g)
@@ -175,17 +181,18 @@ class BruteForce:
         ph = self.ph
         gn = np.sqrt((grad ** 2).sum(0))
         nh = grad / (gn + ph.eps)
-        theta = ph.M / TH * (1 - 4 * (phi - 0.5) ** 2) / ph.W
+        QP, WP, TP = self._phase_lattice()
+        theta = ph.M / TP * (1 - 4 * (phi - 0.5) ** 2) / ph.W
         if ph.mobility_corr:
             s = lap / (np.abs(lap) + ph.eps)
             Fc = lambda x: np.clip(x, 0.0, 1.0)
             Y1 = np.minimum(Fc((phi - ph.phi_M) / ph.D), Fc((1 - phi) / ph.D))
             Y2 = np.minimum(Fc(phi / ph.D), Fc((ph.phi_m - phi) / ph.D))
-            theta = theta + ph.gamma * ph.M / (TH * ph.W) * gn * ((1 + s) * Y1 + (1 - s) * Y2)
-        out = np.zeros((7,) + self.shape)
-        for i in range(7):
+            theta = theta + ph.gamma * ph.M / (TP * ph.W) * gn * ((1 + s) * Y1 + (1 - s) * Y2)
+        out = np.zeros((QP,) + self.shape)
+        for i in range(QP):
             cn = C[i][0] * nh[0] + C[i][1] * nh[1] + C[i][2] * nh[2]
-            out[i] = phi * self._Gamma(WH[i], C[i], u, TH) + theta * WH[i] * cn
+            out[i] = phi * self._Gamma(WP[i], C[i], u, TP) + theta * WP[i] * cn
         return out
 
     def _geq(self, phi, u, P, grad, lap):
@@ -226,7 +233,8 @@ class BruteForce:
                 continue
             P0, ramp = self.wl.faces[f]
             Pb = np.where(self.gface == f, P0 + ramp * t, Pb)
-        h = np.stack([phio * self._Gamma(WH[i], C[i], uo, TH) for i in range(7)])
+        QP, WP, TP = self._phase_lattice()
+        h = np.stack([phio * self._Gamma(WP[i], C[i], uo, TP) for i in range(QP)])
         g = np.stack([rho * self._Gamma(WG[i], C[i], uo, TG) + WG[i] * (Pb / TG - rho)
                       for i in range(19)])
         return h * self.ghost, g * self.ghost
@@ -259,7 +267,8 @@ class BruteForce:
                         for a in range(3) for b in range(3))
             gs[i] = geq[i] + K[i] + omega * WG[i] / (2 * TG * TG) * contr
         heq = self._heq(phi, u, grad, lap)
-        tau_h = ph.M / TH + 0.5
+        QP, WP, TP = self._phase_lattice()
+        tau_h = ph.M / TP + 0.5
         hs = self.h - (self.h - heq) / tau_h
         # ghosts hand over equilibria built from their owners' phi and u of this
         # step and the face pressure of the next step
@@ -281,7 +290,7 @@ class BruteForce:
             cu = C[io][0] * uw[0] + C[io][1] * uw[1] + C[io][2] * uw[2]
             bb = gs[io] - 2 * WG[io] * rho * cu / TG
             gn[i] = np.where(src_solid, bb, shifted(gs[i], C[i], -1))
-            if i < 7:
+            if i < QP:
                 hn[i] = np.where(src_solid, hs[io], shifted(hs[i], C[i], -1))
         hn *= self.fluid
         gn *= self.fluid

@@ -43,6 +43,11 @@ static const double WH[7] = {0.25, 0.125, 0.125, 0.125, 0.125, 0.125, 0.125};
 static const double TG = 1.0 / 3.0; /* lattice temperature of D3Q19 */
 static const double TH = 0.25;      /* lattice temperature of D3Q7 */
 
+/* the phase-field lattice: its size, weights and temperature */
+static int phase_Q(const lbmref_params *p) { return p->q_phase == 19 ? 19 : 7; }
+static const double *phase_w(const lbmref_params *p) { return p->q_phase == 19 ? WG : WH; }
+static double phase_T(const lbmref_params *p) { return p->q_phase == 19 ? TG : TH; }
+
 enum { K_FLUID = 0, K_SOLID = 1, K_GHOST = 2 };
 
 static int opposite(int i) {
@@ -63,7 +68,7 @@ struct lbmref_state {
     long *owner;     /* interior node one step inward from a ghost */
     double *nw;      /* [N*3] unit wall normal into the fluid, 0 without solid links */
     double *hyst;    /* [N*19] wall value each link used last (hysteresis), or NULL */
-    double *h[2];    /* [N*7]  population i of node n at n*7+i */
+    double *h[2];    /* [N*Q] phase population i of node n at n*Q+i (Q = 7 or 19) */
     double *g[2];    /* [N*19] */
     int cur;
     double *phi, *rho, *u, *P, *grad, *lap, *mu;
@@ -205,7 +210,7 @@ double lbmref_dtheta(const lbmref_params *p, double phi, double grad_norm, doubl
     double s = lap / (fabs(lap) + p->eps);
     double Y1 = fmin(fclip((phi - p->phi_M) / p->D), fclip((1.0 - phi) / p->D));
     double Y2 = fmin(fclip(phi / p->D), fclip((p->phi_m - phi) / p->D));
-    return p->gamma * p->M / (TH * p->W) * grad_norm * ((1.0 + s) * Y1 + (1.0 - s) * Y2);
+    return p->gamma * p->M / (phase_T(p) * p->W) * grad_norm * ((1.0 + s) * Y1 + (1.0 - s) * Y2);
 }
 
 /* ----------------------------------------------------------------- wetting */
@@ -294,15 +299,17 @@ static void stencil(lbmref_state *s, long n, double grad[3], double *lap, int hm
 
 /* phase-field equilibrium (Eqs. 2-4), theta including the correction of Eq. 5 */
 static void heq_node(const lbmref_params *p, double phi, const double u[3],
-                     const double grad[3], double lap, double heq[7]) {
+                     const double grad[3], double lap, double heq[19]) {
+    const int Q = phase_Q(p);
+    const double *w = phase_w(p), T = phase_T(p);
     double gn = sqrt(grad[0] * grad[0] + grad[1] * grad[1] + grad[2] * grad[2]);
     double nh[3];
     for (int a = 0; a < 3; ++a) nh[a] = grad[a] / (gn + p->eps);
-    double theta = p->M / TH * (1.0 - 4.0 * (phi - 0.5) * (phi - 0.5)) / p->W;
+    double theta = p->M / T * (1.0 - 4.0 * (phi - 0.5) * (phi - 0.5)) / p->W;
     theta += lbmref_dtheta(p, phi, gn, lap);
-    for (int i = 0; i < 7; ++i) {
+    for (int i = 0; i < Q; ++i) {
         double cn = CV[i][0] * nh[0] + CV[i][1] * nh[1] + CV[i][2] * nh[2];
-        heq[i] = phi * gamma_i(WH[i], CV[i], u, TH) + theta * WH[i] * cn;
+        heq[i] = phi * gamma_i(w[i], CV[i], u, T) + theta * w[i] * cn;
     }
 }
 
@@ -374,10 +381,12 @@ static void ghost_fill(lbmref_state *s, double *hdst, double *gdst, long t) {
 #pragma omp parallel for schedule(static) if (s->N >= 16384)
     for (long n = 0; n < s->N; ++n) {
         if (s->kind[n] != K_GHOST) continue;
-        double *h = &hdst[7 * n], *g = &gdst[19 * n];
+        const int Q = phase_Q(p);
+        const double *w = phase_w(p), T = phase_T(p);
+        double *h = &hdst[(long)Q * n], *g = &gdst[19 * n];
         long o = s->owner[n];
         if (o < 0) {
-            for (int i = 0; i < 7; ++i) h[i] = 0.0;
+            for (int i = 0; i < Q; ++i) h[i] = 0.0;
             for (int i = 0; i < 19; ++i) g[i] = 0.0;
             continue;
         }
@@ -385,7 +394,7 @@ static void ghost_fill(lbmref_state *s, double *hdst, double *gdst, long t) {
         const double *u = &s->u[3 * o];
         double rho = density(p, ph);
         double Pb = pressure_at_face(p, s->gface[n], t);
-        for (int i = 0; i < 7; ++i) h[i] = ph * gamma_i(WH[i], CV[i], u, TH);
+        for (int i = 0; i < Q; ++i) h[i] = ph * gamma_i(w[i], CV[i], u, T);
         for (int i = 0; i < 19; ++i)
             g[i] = rho * gamma_i(WG[i], CV[i], u, TG) + WG[i] * (Pb / TG - rho);
     }
@@ -394,11 +403,12 @@ static void ghost_fill(lbmref_state *s, double *hdst, double *gdst, long t) {
 /* S1: order parameter on fluid nodes, then Neumann copy to ghosts */
 static void phase_moment(lbmref_state *s) {
     const double *h = s->h[s->cur];
+    const int Q = phase_Q(&s->p);
 #pragma omp parallel for schedule(static) if (s->N >= 16384)
     for (long n = 0; n < s->N; ++n) {
         double v = 0.0;
         if (s->kind[n] == K_FLUID)
-            for (int i = 0; i < 7; ++i) v += h[7 * n + i];
+            for (int i = 0; i < Q; ++i) v += h[(long)Q * n + i];
         s->phi[n] = v;
     }
 #pragma omp parallel for schedule(static) if (s->N >= 16384)
@@ -445,7 +455,7 @@ lbmref_state *lbmref_create(const lbmref_params *p, const uint8_t *solid,
     s->nw = malloc(3 * N * sizeof(double));
     s->hyst = p->hysteresis ? calloc(19 * N, sizeof(double)) : NULL;
     for (int k = 0; k < 2; ++k) {
-        s->h[k] = calloc(7 * N, sizeof(double));
+        s->h[k] = calloc((long)phase_Q(p) * N, sizeof(double));
         s->g[k] = calloc(19 * N, sizeof(double));
     }
     s->phi = calloc(N, sizeof(double)); s->rho = calloc(N, sizeof(double));
@@ -475,10 +485,10 @@ lbmref_state *lbmref_create(const lbmref_params *p, const uint8_t *solid,
         stencil(s, n, grad, &lap, HYST_SET);
         for (int a = 0; a < 3; ++a) u[a] = u0 ? u0[a * N + n] : 0.0;
         P = P0 ? P0[n] : p->P_ref;
-        double heq[7], geq[19], K[19];
+        double heq[19], geq[19], K[19];
         heq_node(p, s->phi[n], u, grad, lap, heq);
         lbmref_geq_node(p, s->phi[n], u, P, grad, lap, geq, K);
-        for (int i = 0; i < 7; ++i) h[7 * n + i] = heq[i];
+        for (int i = 0; i < phase_Q(p); ++i) h[(long)phase_Q(p) * n + i] = heq[i];
         for (int i = 0; i < 19; ++i) g[19 * n + i] = geq[i];
         for (int a = 0; a < 3; ++a) s->u[3 * n + a] = u[a];
     }
@@ -510,13 +520,14 @@ static void one_step(lbmref_state *s) {
 #pragma omp parallel for schedule(static) if (s->N >= 16384)
     for (long n = 0; n < N; ++n) {
         if (s->kind[n] != K_FLUID) continue;
-        double grad[3], lap, u[3], P, gout[19], heq[7];
+        double grad[3], lap, u[3], P, gout[19], heq[19];
         stencil(s, n, grad, &lap, HYST_STEP);
         double ph = s->phi[n];
         lbmref_collide_g_node(p, &gA[19 * n], ph, grad, lap, gout, u, &P);
         heq_node(p, ph, u, grad, lap, heq);
-        double tau_h = p->M / TH + 0.5;
-        for (int i = 0; i < 7; ++i) hA[7 * n + i] -= (hA[7 * n + i] - heq[i]) / tau_h;
+        const int Q = phase_Q(p);
+        double tau_h = p->M / phase_T(p) + 0.5;
+        for (int i = 0; i < Q; ++i) hA[(long)Q * n + i] -= (hA[(long)Q * n + i] - heq[i]) / tau_h;
         for (int i = 0; i < 19; ++i) gA[19 * n + i] = gout[i];
         for (int a = 0; a < 3; ++a) s->u[3 * n + a] = u[a];
         s->rho[n] = density(p, ph);
@@ -527,6 +538,7 @@ static void one_step(lbmref_state *s) {
      * one-step lag in phi and u; ghosts are never collided) */
     ghost_fill(s, hA, gA, s->step + 1);
     /* S8: pull into lattice B */
+    const int Qh = phase_Q(p);
 #pragma omp parallel for schedule(static) if (s->N >= 16384)
     for (long y = 0; y < N; ++y) {
         if (s->kind[y] != K_FLUID) continue;
@@ -546,10 +558,10 @@ static void one_step(lbmref_state *s) {
             if (s->kind[x] == K_SOLID) {
                 double cu = CV[io][0] * uw[0] + CV[io][1] * uw[1] + CV[io][2] * uw[2];
                 gv = gA[19 * y + io] - 2.0 * WG[io] * s->rho[y] * cu / TG;
-                if (i < 7) hB[7 * y + i] = hA[7 * y + io];
+                if (i < Qh) hB[(long)Qh * y + i] = hA[(long)Qh * y + io];
             } else {
                 gv = gA[19 * x + i];
-                if (i < 7) hB[7 * y + i] = hA[7 * x + i];
+                if (i < Qh) hB[(long)Qh * y + i] = hA[(long)Qh * x + i];
             }
             gB[19 * y + i] = gv;
         }
@@ -590,7 +602,7 @@ void lbmref_pops(const lbmref_state *s, double *h, double *g) {
     for (long n = 0; n < N; ++n) {
         int fl = (s->kind[n] == K_FLUID);
         if (h)
-            for (int i = 0; i < 7; ++i) h[i * N + n] = fl ? hA[7 * n + i] : 0.0;
+            for (int i = 0; i < phase_Q(&s->p); ++i) h[i * N + n] = fl ? hA[(long)phase_Q(&s->p) * n + i] : 0.0;
         if (g)
             for (int i = 0; i < 19; ++i) g[i * N + n] = fl ? gA[19 * n + i] : 0.0;
     }
@@ -601,7 +613,7 @@ void lbmref_set_pops(lbmref_state *s, const double *h, const double *g, long ste
     double *hA = s->h[s->cur], *gA = s->g[s->cur];
     for (long n = 0; n < N; ++n) {
         if (s->kind[n] != K_FLUID) continue;
-        for (int i = 0; i < 7; ++i) hA[7 * n + i] = h[i * N + n];
+        for (int i = 0; i < phase_Q(&s->p); ++i) hA[(long)phase_Q(&s->p) * n + i] = h[i * N + n];
         for (int i = 0; i < 19; ++i) gA[19 * n + i] = g[i * N + n];
     }
     s->step = step;

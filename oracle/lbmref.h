@@ -58,6 +58,9 @@ typedef struct lbmref_params {
      * phi_s,i = beta * previous + (1 - beta) * phi_s,i (current gradient) */
     int hysteresis;
     double hyst_beta;
+    /* phase-field lattice: 7 (D3Q7, T = 1/4) or 19 (D3Q19, T = 1/3, as the
+     * paper writes Eqs. 1-4); 0 means 7 */
+    int q_phase;
 } lbmref_params;
 
 typedef struct lbmref_diag {
@@ -83,8 +86,9 @@ void lbmref_kinds(const lbmref_state *s, uint8_t *kind);
 /* phi, P, u at the current step (any may be NULL).  Solid: 0.  Ghost: phi of
  * the owner, P = the face pressure at this step, u = 0. */
 void lbmref_fields(lbmref_state *s, double *phi, double *P, double *u);
-/* populations f_i(x) entering the collision of the current step, [7][N] and
- * [19][N]; zero at solid and ghost nodes. */
+/* populations f_i(x) entering the collision of the current step, h [Q][N]
+ * (Q = 7 or 19, the phase lattice) and g [19][N]; zero at solid and ghost
+ * nodes. */
 void lbmref_pops(const lbmref_state *s, double *h, double *g);
 /* overwrite fluid-node populations (restore); ghosts keep their values */
 void lbmref_set_pops(lbmref_state *s, const double *h, const double *g, long step);

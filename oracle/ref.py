@@ -50,6 +50,7 @@ class Params(ctypes.Structure):
         ("theta_deg", ctypes.c_double * 16),
         ("clamp_a", ctypes.c_double),
         ("hysteresis", ctypes.c_int), ("hyst_beta", ctypes.c_double),
+        ("q_phase", ctypes.c_int),
     ]
 
 
@@ -125,6 +126,7 @@ def make_params(wl, clamp_a=1e-12):
     p.clamp_a = clamp_a
     p.hysteresis = int(getattr(ph, "hysteresis", False))
     p.hyst_beta = getattr(ph, "hyst_beta", 0.0)
+    p.q_phase = int(getattr(ph, "q_phase", 7))
     return p
 
 
@@ -175,7 +177,7 @@ class Oracle:
         return phi, P, u
 
     def pops(self):
-        h = np.zeros((7,) + self.shape)
+        h = np.zeros((int(getattr(self.wl.phys, "q_phase", 7)),) + self.shape)
         g = np.zeros((19,) + self.shape)
         lib().lbmref_pops(self.h, _dptr(h), _dptr(g))
         return h, g

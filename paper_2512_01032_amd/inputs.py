@@ -59,6 +59,7 @@ class Physics:
     P_ref: float = T_G
     hysteresis: bool = False        # Sec. III.A: wall values blended with the previous step's
     hyst_beta: float = 0.95
+    q_phase: int = 7                # phase-field lattice: 7 (D3Q7) or 19 (D3Q19, as in Sec. II.A)
 
 
 def optimised(ph: Physics, hysteresis: bool = False) -> Physics:

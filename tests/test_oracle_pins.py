@@ -25,18 +25,18 @@ def relmax(a, b):
 
 
 # --------------------------------------------------------------------- P1
-@pytest.mark.parametrize("kw,hyst", [(dict(), False), (dict(walls=True), False),
-                                     (dict(walls=True, open_x=True), False),
-                                     (dict(walls=True, open_x=True, optimised_model=True), False),
-                                     (dict(walls=True, open_x=True, optimised_model=True), True)])
-def test_bruteforce_reference_agrees(kw, hyst):
+@pytest.mark.parametrize("kw,hyst,q", [(dict(), False, 7), (dict(walls=True), False, 7),
+                                       (dict(walls=True, open_x=True), False, 7),
+                                       (dict(walls=True, open_x=True, optimised_model=True), False, 7),
+                                       (dict(walls=True, open_x=True, optimised_model=True), True, 7),
+                                       (dict(walls=True, open_x=True, optimised_model=True), False, 19)])
+def test_bruteforce_reference_agrees(kw, hyst, q):
     """Whole-lattice NumPy transcription (np.roll streaming, masks) vs the
     node-by-node C oracle on a tiny lattice: pins indexing, periodic wrap,
     bounce-back, wall normals and ghost bookkeeping, and (hyst) the history
     of the wall values, whose first blend only shows from the second step."""
     wl = I.random_small(8, 6, 7, seed=3, **kw)
-    if hyst:
-        wl.phys = dataclasses.replace(wl.phys, hysteresis=True, hyst_beta=0.95)
+    wl.phys = dataclasses.replace(wl.phys, hysteresis=hyst, hyst_beta=0.95, q_phase=q)
     o = ref.Oracle(wl)
     b = bruteforce.BruteForce(wl)
     o.step(6)
@@ -51,12 +51,14 @@ def test_bruteforce_reference_agrees(kw, hyst):
 
 
 # ---------------------------------------------------------------- P2, P12
-def test_mass_conservation_and_cubic_symmetry_c1():
-    """Static droplet (32^3, 200 steps): sum phi is conserved to rounding
-    (bounce-free periodic box; sum_i h_eq,i = phi and sum_i w_i c_i = 0), and
-    the field keeps the cubic symmetry of the initial droplet (a transposed
-    or mis-signed stencil term breaks it)."""
+@pytest.mark.parametrize("q", [7, 19])
+def test_mass_conservation_and_cubic_symmetry_c1(q):
+    """Static droplet (32^3, 200 steps), D3Q7 and D3Q19 phase lattices: sum
+    phi is conserved to rounding (bounce-free periodic box; sum_i h_eq,i =
+    phi and sum_i w_i c_i = 0), and the field keeps the cubic symmetry of the
+    initial droplet (a transposed or mis-signed stencil term breaks it)."""
     wl = I.static_droplet()
+    wl.phys = dataclasses.replace(wl.phys, q_phase=q)
     o = ref.Oracle(wl)
     m0 = o.diagnostics()["phi_sum"]
     o.step(200)
@@ -80,8 +82,8 @@ def test_mass_conservation_with_walls():
 
 
 # --------------------------------------------------------------------- P3
-def _slab(W, n=64, u=0.0, rho_g=0.001, nu_g=0.1):
-    ph = I.Physics(W=W, rho_g=rho_g, nu_g=nu_g)
+def _slab(W, n=64, u=0.0, rho_g=0.001, nu_g=0.1, q=7):
+    ph = I.Physics(W=W, rho_g=rho_g, nu_g=nu_g, q_phase=q)
     x = np.arange(n, dtype=float)
     phz = 0.5 * (np.tanh((x - 15.5) / (W / 2)) - np.tanh((x - 47.5) / (W / 2)))
     u0 = None
@@ -91,15 +93,17 @@ def _slab(W, n=64, u=0.0, rho_g=0.001, nu_g=0.1):
     return I.Workload("slab", n, 1, 1, ph, phz[None, None, :].copy(), u0=u0), phz
 
 
-def test_planar_interface_is_stationary_and_second_order():
+@pytest.mark.parametrize("q", [7, 19])
+def test_planar_interface_is_stationary_and_second_order(q):
     """The tanh profile (Sec. II.B, Eq. 17) is the stationary solution of the
     conservative Allen-Cahn equation: the counter-term theta w_i c_i.n must
     balance diffusion.  A wrong sign of theta or of n makes the interface
-    spread; a wrong factor makes it drift to another width.  The discrete
-    profile converges to tanh at second order in 1/W."""
+    spread; a wrong factor (e.g. the other lattice's temperature in theta or
+    tau_h) makes it drift to another width.  The discrete profile converges
+    to tanh at second order in 1/W, on either phase lattice."""
     errs = {}
     for W in (4.0, 8.0):
-        wl, phz = _slab(W)
+        wl, phz = _slab(W, q=q)
         o = ref.Oracle(wl)
         o.step(2000)
         p1 = o.fields()[0].ravel()
