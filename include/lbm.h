@@ -23,7 +23,8 @@
  * Conventions
  *   Node index n = x + nx*(y + ny*z).  Scalar fields are arrays of N doubles,
  *   vector fields [3][N] (all x components, then y, then z), populations
- *   [Q][N].  Lattice order of the populations (phase field uses the first 7):
+ *   [Q][N].  Lattice order of the populations (a D3Q7 phase field uses the
+ *   first 7):
  *     0:(0,0,0) 1:(+1,0,0) 2:(-1,0,0) 3:(0,+1,0) 4:(0,-1,0) 5:(0,0,+1) 6:(0,0,-1)
  *     7:(+1,+1,0) 8:(-1,-1,0) 9:(+1,-1,0) 10:(-1,+1,0) 11:(+1,0,+1) 12:(-1,0,-1)
  *     13:(+1,0,-1) 14:(-1,0,+1) 15:(0,+1,+1) 16:(0,-1,-1) 17:(0,+1,-1) 18:(0,-1,+1)
@@ -96,6 +97,9 @@ typedef struct lbm_params {
                                gradient) and keeps the result; the history starts from the
                                current values at creation and after a restore */
     double hyst_beta;       /* blend factor in [0, 1) (the paper's 0.95) */
+    int32_t q_phase;        /* phase-field lattice: 7 (D3Q7, T = 1/4, the default; 0 means 7)
+                               or 19 (D3Q19 with the hydrodynamic weights, T = 1/3, the
+                               lattice Sec. II names for Eq. 2); any other value: LBM_E_INVAL */
 } lbm_params;
 
 /* Voxel geometry.  solid[n] = 0: fluid; 1 + k: solid of material k (< 16).
@@ -113,7 +117,7 @@ enum lbm_init_kind { LBM_INIT_FIELDS = 0, LBM_INIT_POPULATIONS = 1 };
 /* Initial state.  FIELDS: phi[N] required, u[3][N] may be NULL (0), P[N] may
  * be NULL (P_ref); populations are set to their equilibria with the wetting
  * stencil applied (h with the counter-term, g with K_i).  POPULATIONS: pops =
- * h[7][N] followed by g[19][N] as returned by lbm_read_fields(LBM_POP_H |
+ * h[q_phase][N] followed by g[19][N] as returned by lbm_read_fields(LBM_POP_H |
  * LBM_POP_G) and step = the step they belong to (restore). Host memory, read
  * during the call only. */
 typedef struct lbm_init {
@@ -184,7 +188,7 @@ int64_t lbm_step_count(const lbm_handle *h);
  * phi[N], P[N], u[3][N]: macroscopic fields of the current step, evaluated
  * from the populations entering its collision (after the text of Eq. 15).
  * Solid nodes read 0; ghosts read the owner's phi, the face pressure and 0.
- * pops: h[7][N] (if LBM_POP_H) then g[19][N] (if LBM_POP_G), decoded to double,
+ * pops: h[q_phase][N] (if LBM_POP_H) then g[19][N] (if LBM_POP_G), decoded to double,
  * the value f_i(x) entering the collision; 0 at solid and ghost nodes. */
 int lbm_read_fields(lbm_handle *h, uint32_t mask, double *phi, double *P, double *u,
                     double *pops);

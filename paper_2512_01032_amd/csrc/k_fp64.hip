@@ -4,23 +4,24 @@
 
 namespace pflbm {
 
-hipError_t launch_sweep_fp64(int mode, int tx, int parity, Desc* d, const Tile* tiles, int ntiles,
-                          int diag, ReadOut ro, InitIn in, hipStream_t s) {
-    return launch_sweep_storage<double, double, double>(mode, tx, parity, d, tiles, ntiles, diag, ro, in, s);
+hipError_t launch_sweep_fp64(int qp, int mode, int tx, int parity, Desc* d, const Tile* tiles,
+                          int ntiles, int diag, ReadOut ro, InitIn in, hipStream_t s) {
+    return launch_sweep_storage<double, double, double>(qp, mode, tx, parity, d, tiles, ntiles, diag, ro, in, s);
 }
 
-hipError_t launch_phi_fp64(int parity, const Desc* d, const Tile* tiles, int ntiles, hipStream_t s,
-                        int force) {
-    return launch_phi_storage<double, double>(parity, d, tiles, ntiles, s, force);
+hipError_t launch_phi_fp64(int qp, int parity, const Desc* d, const Tile* tiles, int ntiles,
+                        hipStream_t s, int force) {
+    return launch_phi_storage<double, double>(qp, parity, d, tiles, ntiles, s, force);
 }
 
-hipError_t launch_restore_fp64(int parity, const Desc* d, const Tile* tiles, int ntiles,
+hipError_t launch_restore_fp64(int qp, int parity, const Desc* d, const Tile* tiles, int ntiles,
                             const double* pops, hipStream_t s) {
-    return launch_restore_storage<double, double, double>(parity, d, tiles, ntiles, pops, s);
+    return launch_restore_storage<double, double, double>(qp, parity, d, tiles, ntiles, pops, s);
 }
 
-hipError_t launch_ghosts_fp64(const Desc* d, const GhostRef* ghosts, int nghosts, hipStream_t s) {
-    return launch_ghosts_storage<double, double, double>(d, ghosts, nghosts, s);
+hipError_t launch_ghosts_fp64(int qp, const Desc* d, const GhostRef* ghosts, int nghosts,
+                           hipStream_t s) {
+    return launch_ghosts_storage<double, double, double>(qp, d, ghosts, nghosts, s);
 }
 
 }  // namespace pflbm

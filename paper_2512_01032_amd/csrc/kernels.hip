@@ -22,67 +22,67 @@ hipError_t launch_advance(Desc* d, int nlat, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_sweep_fp64(int, int, int, Desc*, const Tile*, int, int, ReadOut, InitIn, hipStream_t);
-hipError_t launch_phi_fp64(int, const Desc*, const Tile*, int, hipStream_t, int);
-hipError_t launch_restore_fp64(int, const Desc*, const Tile*, int, const double*, hipStream_t);
-hipError_t launch_ghosts_fp64(const Desc*, const GhostRef*, int, hipStream_t);
-hipError_t launch_sweep_fp32(int, int, int, Desc*, const Tile*, int, int, ReadOut, InitIn, hipStream_t);
-hipError_t launch_phi_fp32(int, const Desc*, const Tile*, int, hipStream_t, int);
-hipError_t launch_restore_fp32(int, const Desc*, const Tile*, int, const double*, hipStream_t);
-hipError_t launch_ghosts_fp32(const Desc*, const GhostRef*, int, hipStream_t);
-hipError_t launch_sweep_fp16g(int, int, int, Desc*, const Tile*, int, int, ReadOut, InitIn, hipStream_t);
-hipError_t launch_phi_fp16g(int, const Desc*, const Tile*, int, hipStream_t, int);
-hipError_t launch_restore_fp16g(int, const Desc*, const Tile*, int, const double*, hipStream_t);
-hipError_t launch_ghosts_fp16g(const Desc*, const GhostRef*, int, hipStream_t);
-hipError_t launch_sweep_fp16a(int, int, int, Desc*, const Tile*, int, int, ReadOut, InitIn, hipStream_t);
-hipError_t launch_phi_fp16a(int, const Desc*, const Tile*, int, hipStream_t, int);
-hipError_t launch_restore_fp16a(int, const Desc*, const Tile*, int, const double*, hipStream_t);
-hipError_t launch_ghosts_fp16a(const Desc*, const GhostRef*, int, hipStream_t);
+hipError_t launch_sweep_fp64(int, int, int, int, Desc*, const Tile*, int, int, ReadOut, InitIn, hipStream_t);
+hipError_t launch_phi_fp64(int, int, const Desc*, const Tile*, int, hipStream_t, int);
+hipError_t launch_restore_fp64(int, int, const Desc*, const Tile*, int, const double*, hipStream_t);
+hipError_t launch_ghosts_fp64(int, const Desc*, const GhostRef*, int, hipStream_t);
+hipError_t launch_sweep_fp32(int, int, int, int, Desc*, const Tile*, int, int, ReadOut, InitIn, hipStream_t);
+hipError_t launch_phi_fp32(int, int, const Desc*, const Tile*, int, hipStream_t, int);
+hipError_t launch_restore_fp32(int, int, const Desc*, const Tile*, int, const double*, hipStream_t);
+hipError_t launch_ghosts_fp32(int, const Desc*, const GhostRef*, int, hipStream_t);
+hipError_t launch_sweep_fp16g(int, int, int, int, Desc*, const Tile*, int, int, ReadOut, InitIn, hipStream_t);
+hipError_t launch_phi_fp16g(int, int, const Desc*, const Tile*, int, hipStream_t, int);
+hipError_t launch_restore_fp16g(int, int, const Desc*, const Tile*, int, const double*, hipStream_t);
+hipError_t launch_ghosts_fp16g(int, const Desc*, const GhostRef*, int, hipStream_t);
+hipError_t launch_sweep_fp16a(int, int, int, int, Desc*, const Tile*, int, int, ReadOut, InitIn, hipStream_t);
+hipError_t launch_phi_fp16a(int, int, const Desc*, const Tile*, int, hipStream_t, int);
+hipError_t launch_restore_fp16a(int, int, const Desc*, const Tile*, int, const double*, hipStream_t);
+hipError_t launch_ghosts_fp16a(int, const Desc*, const GhostRef*, int, hipStream_t);
 
-hipError_t launch_sweep(int storage, int mode, int tx, int parity, Desc* d, const Tile* tiles,
+hipError_t launch_sweep(int storage, int qp, int mode, int tx, int parity, Desc* d, const Tile* tiles,
                         int ntiles, int diag, ReadOut ro, InitIn in, hipStream_t s) {
     switch (storage) {
-        case ST_FP64: return launch_sweep_fp64(mode, tx, parity, d, tiles, ntiles, diag, ro, in, s);
+        case ST_FP64: return launch_sweep_fp64(qp, mode, tx, parity, d, tiles, ntiles, diag, ro, in, s);
         case ST_FP32:
-        case ST_FP32_SHIFT: return launch_sweep_fp32(mode, tx, parity, d, tiles, ntiles, diag, ro, in, s);
-        case ST_FP16_G: return launch_sweep_fp16g(mode, tx, parity, d, tiles, ntiles, diag, ro, in, s);
-        case ST_FP16_ALL: return launch_sweep_fp16a(mode, tx, parity, d, tiles, ntiles, diag, ro, in, s);
+        case ST_FP32_SHIFT: return launch_sweep_fp32(qp, mode, tx, parity, d, tiles, ntiles, diag, ro, in, s);
+        case ST_FP16_G: return launch_sweep_fp16g(qp, mode, tx, parity, d, tiles, ntiles, diag, ro, in, s);
+        case ST_FP16_ALL: return launch_sweep_fp16a(qp, mode, tx, parity, d, tiles, ntiles, diag, ro, in, s);
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_phi(int storage, int parity, const Desc* d, const Tile* tiles, int ntiles,
+hipError_t launch_phi(int storage, int qp, int parity, const Desc* d, const Tile* tiles, int ntiles,
                       hipStream_t s, int force) {
     switch (storage) {
-        case ST_FP64: return launch_phi_fp64(parity, d, tiles, ntiles, s, force);
+        case ST_FP64: return launch_phi_fp64(qp, parity, d, tiles, ntiles, s, force);
         case ST_FP32:
-        case ST_FP32_SHIFT: return launch_phi_fp32(parity, d, tiles, ntiles, s, force);
-        case ST_FP16_G: return launch_phi_fp16g(parity, d, tiles, ntiles, s, force);
-        case ST_FP16_ALL: return launch_phi_fp16a(parity, d, tiles, ntiles, s, force);
+        case ST_FP32_SHIFT: return launch_phi_fp32(qp, parity, d, tiles, ntiles, s, force);
+        case ST_FP16_G: return launch_phi_fp16g(qp, parity, d, tiles, ntiles, s, force);
+        case ST_FP16_ALL: return launch_phi_fp16a(qp, parity, d, tiles, ntiles, s, force);
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_restore(int storage, int parity, const Desc* d, const Tile* tiles, int ntiles,
+hipError_t launch_restore(int storage, int qp, int parity, const Desc* d, const Tile* tiles, int ntiles,
                           const double* pops, hipStream_t s) {
     switch (storage) {
-        case ST_FP64: return launch_restore_fp64(parity, d, tiles, ntiles, pops, s);
+        case ST_FP64: return launch_restore_fp64(qp, parity, d, tiles, ntiles, pops, s);
         case ST_FP32:
-        case ST_FP32_SHIFT: return launch_restore_fp32(parity, d, tiles, ntiles, pops, s);
-        case ST_FP16_G: return launch_restore_fp16g(parity, d, tiles, ntiles, pops, s);
-        case ST_FP16_ALL: return launch_restore_fp16a(parity, d, tiles, ntiles, pops, s);
+        case ST_FP32_SHIFT: return launch_restore_fp32(qp, parity, d, tiles, ntiles, pops, s);
+        case ST_FP16_G: return launch_restore_fp16g(qp, parity, d, tiles, ntiles, pops, s);
+        case ST_FP16_ALL: return launch_restore_fp16a(qp, parity, d, tiles, ntiles, pops, s);
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_ghosts(int storage, const Desc* d, const GhostRef* ghosts, int nghosts,
+hipError_t launch_ghosts(int storage, int qp, const Desc* d, const GhostRef* ghosts, int nghosts,
                          hipStream_t s) {
     switch (storage) {
-        case ST_FP64: return launch_ghosts_fp64(d, ghosts, nghosts, s);
+        case ST_FP64: return launch_ghosts_fp64(qp, d, ghosts, nghosts, s);
         case ST_FP32:
-        case ST_FP32_SHIFT: return launch_ghosts_fp32(d, ghosts, nghosts, s);
-        case ST_FP16_G: return launch_ghosts_fp16g(d, ghosts, nghosts, s);
-        case ST_FP16_ALL: return launch_ghosts_fp16a(d, ghosts, nghosts, s);
+        case ST_FP32_SHIFT: return launch_ghosts_fp32(qp, d, ghosts, nghosts, s);
+        case ST_FP16_G: return launch_ghosts_fp16g(qp, d, ghosts, nghosts, s);
+        case ST_FP16_ALL: return launch_ghosts_fp16a(qp, d, ghosts, nghosts, s);
     }
     return hipErrorInvalidValue;
 }

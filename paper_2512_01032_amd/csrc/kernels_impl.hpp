@@ -51,6 +51,13 @@ constexpr int CZ[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -
 constexpr int OPP[19] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
 __host__ __device__ constexpr double wg(int i) { return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0); }
 __host__ __device__ constexpr double wh(int i) { return i == 0 ? 0.25 : 0.125; }
+// phase lattice of QP directions: weights and the inverse-temperature
+// factors 1/T, 1/(2T^2), 1/(2T) of its second-order equilibrium (D3Q7:
+// T = 1/4, D3Q19: T = 1/3)
+template <int QP> __host__ __device__ constexpr double wp(int i) { return QP == 19 ? wg(i) : wh(i); }
+template <int QP> __host__ __device__ constexpr double itp() { return QP == 19 ? 3.0 : 4.0; }
+template <int QP> __host__ __device__ constexpr double i2tp2() { return QP == 19 ? 4.5 : 8.0; }
+template <int QP> __host__ __device__ constexpr double i2tp() { return QP == 19 ? 1.5 : 2.0; }
 constexpr double TGc = 1.0 / 3.0;  // D3Q19 lattice temperature
 constexpr double THc = 0.25;       // D3Q7 lattice temperature
 
@@ -243,23 +250,23 @@ __device__ inline void place_pops(const PopArray<S, Q>& a, uint32_t n, const Nbr
 }
 
 // ------------------------------------------------------------------ phi pass
-template <typename T, typename SH, int PAR>
-__device__ inline T phase_sum(const PopArray<SH, QH>& h, const uint8_t* flg, const uint32_t* lnk,
+template <typename T, typename SH, int PAR, int QP>
+__device__ inline T phase_sum(const PopArray<SH, QP>& h, const uint8_t* flg, const uint32_t* lnk,
                               int n, int x, int y, int z, int nx, int ny, int nz,
                               const Phys<T>& ph) {
     const uint8_t f = flg[n];
     const uint32_t solid = (PAR == 1 && (f & F_NEAR_WALL)) ? (lnk[n] & SOLID_MASK) : 0u;
     Nbr nb;
     nb.init(x, y, z, nx, ny, nz);
-    T d[QH];
-    read_pops<T, SH, QH, PAR>(h, (uint32_t)n, nb, solid, ph[PI_INV_SH], d);
+    T d[QP];
+    read_pops<T, SH, QP, PAR>(h, (uint32_t)n, nb, solid, ph[PI_INV_SH], d);
     T s = T(0);
 #pragma unroll
-    for (int i = 0; i < QH; ++i) s += d[i];
+    for (int i = 0; i < QP; ++i) s += d[i];
     return ph[PI_HREF] + s;
 }
 
-template <typename T, typename SH, int PAR>
+template <typename T, typename SH, int PAR, int QP>
 __global__ void __launch_bounds__(NTHREADS)
 phi_kernel(const Desc* __restrict__ descs, const Tile* __restrict__ tiles, int force) {
     const Tile tl = load_tile(tiles);
@@ -272,7 +279,7 @@ phi_kernel(const Desc* __restrict__ descs, const Tile* __restrict__ tiles, int f
     if (x >= nx || y >= ny) return;
     Phys<T> ph;
     ph.load(D);
-    const PopArray<SH, QH> h = pop_array<SH, QH>(D->h, uni(D->N));
+    const PopArray<SH, QP> h = pop_array<SH, QP>(D->h, uni(D->N));
     const uint8_t* __restrict__ flg = unip(D->flag);
     const uint32_t* __restrict__ lnk = unip(D->link);
     T* __restrict__ phi = unip((T*)D->phi);
@@ -283,7 +290,7 @@ phi_kernel(const Desc* __restrict__ descs, const Tile* __restrict__ tiles, int f
         const int kind = flag_kind(f);
         T v = T(0);
         if (kind == KIND_FLUID) {
-            v = phase_sum<T, SH, PAR>(h, flg, lnk, n, x, y, z, nx, ny, nz, ph);
+            v = phase_sum<T, SH, PAR, QP>(h, flg, lnk, n, x, y, z, nx, ny, nz, ph);
         } else if (kind == KIND_GHOST) {
             // owner = one step inward along the face normal
             const int face = flag_sub(f);
@@ -291,7 +298,7 @@ phi_kernel(const Desc* __restrict__ descs, const Tile* __restrict__ tiles, int f
             int ox = x, oy = y, oz = z;
             if (ax == 0) ox += sg; else if (ax == 1) oy += sg; else oz += sg;
             const int o = ox + nx * (oy + ny * oz);
-            v = phase_sum<T, SH, PAR>(h, flg, lnk, o, ox, oy, oz, nx, ny, nz, ph);
+            v = phase_sum<T, SH, PAR, QP>(h, flg, lnk, o, ox, oy, oz, nx, ny, nz, ph);
         }
         phi[n] = v;
     }
@@ -384,14 +391,14 @@ __device__ inline void g_out_pair(int i, const NodeState<T>& s, T rdif, T& vp, T
     vm = bm + T(0.5) * Km + filt;
 }
 
-// D3Q7 equilibrium deviation of the pair (i, opp(i)) (Eqs. 2-4):
+// Phase-field equilibrium deviation of the pair (i, opp(i)) (Eqs. 2-4):
 // h_eq_i - w_i href = w_i [(phi - href) + phi gam^h_i + theta c_i.n]
-template <typename T>
+template <typename T, int QP>
 __device__ inline void h_eq_pair(int i, const NodeState<T>& s, T href, T& hp, T& hm) {
-    const T w = T(wh(i));
+    const T w = T(wp<QP>(i));
     const T a = cdot(i, s.u[0], s.u[1], s.u[2]);
-    const T e = (s.pc - href) + s.pc * (T(8) * a * a - T(2) * s.uu);
-    const T o = s.pc * T(4) * a + cdot(i, s.tn[0], s.tn[1], s.tn[2]);
+    const T e = (s.pc - href) + s.pc * (T(i2tp2<QP>()) * a * a - T(i2tp<QP>()) * s.uu);
+    const T o = s.pc * T(itp<QP>()) * a + cdot(i, s.tn[0], s.tn[1], s.tn[2]);
     hp = w * (e + o);
     hm = w * (e - o);
 }
@@ -399,7 +406,7 @@ __device__ inline void h_eq_pair(int i, const NodeState<T>& s, T href, T& hp, T&
 #ifndef SWEEP_WAVES_PER_EU
 #define SWEEP_WAVES_PER_EU 1
 #endif
-template <typename T, typename SH, typename SG, int MODE, bool DIAG, int TX, int PAR>
+template <typename T, typename SH, typename SG, int MODE, bool DIAG, int TX, int PAR, int QP>
 __global__ void __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(SWEEP_WAVES_PER_EU)))
 sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut ro, InitIn in) {
     // LDS ring of phi and flags: each plane holds the tile plus a one-node
@@ -431,7 +438,7 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
     const T* __restrict__ phig = unip((const T*)D->phi);
     const uint8_t* __restrict__ flg = unip(D->flag);
     const uint32_t* __restrict__ lnk = unip(D->link);
-    const PopArray<SH, QH> hb = pop_array<SH, QH>(D->h, N);
+    const PopArray<SH, QP> hb = pop_array<SH, QP>(D->h, N);
     const PopArray<SG, QG> gb = pop_array<SG, QG>(D->g, N);
     const T Tg = T(TGc);
     const T iTg = T(3), i2Tg2 = T(4.5);
@@ -503,7 +510,7 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
                 if (ro.P) ro.P[n] = Pv;
                 if (ro.u) { ro.u[n] = 0.0; ro.u[N + n] = 0.0; ro.u[2 * N + n] = 0.0; }
                 if (ro.pops)
-                    for (int i = 0; i < QH + QG; ++i) ro.pops[(int64_t)i * N + n] = 0.0;
+                    for (int i = 0; i < QP + QG; ++i) ro.pops[(int64_t)i * N + n] = 0.0;
             }
             continue;
         }
@@ -647,7 +654,7 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
                               (st.u[0] * st.grad[0] + st.u[1] * st.grad[1] + st.u[2] * st.grad[2]);
             if (MODE == MODE_READ && ro.pops) {
                 for (int i = 0; i < QG; ++i)
-                    ro.pops[(int64_t)(QH + i) * N + n] = (double)(T(wg(i)) * ph[PI_GREF] + dg[i]);
+                    ro.pops[(int64_t)(QP + i) * N + n] = (double)(T(wg(i)) * ph[PI_GREF] + dg[i]);
             }
         }
         st.uu = st.u[0] * st.u[0] + st.u[1] * st.u[1] + st.u[2] * st.u[2];
@@ -658,10 +665,10 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
             if (ro.P) ro.P[n] = (double)P;
             if (ro.u) { ro.u[n] = (double)st.u[0]; ro.u[N + n] = (double)st.u[1]; ro.u[2 * N + n] = (double)st.u[2]; }
             if (ro.pops) {
-                T dh[QH];
-                read_pops<T, SH, QH, PAR>(hb, (uint32_t)n, nb, solid, ph[PI_INV_SH], dh);
-                for (int i = 0; i < QH; ++i)
-                    ro.pops[(int64_t)i * N + n] = (double)(T(wh(i)) * ph[PI_HREF] + dh[i]);
+                T dh[QP];
+                read_pops<T, SH, QP, PAR>(hb, (uint32_t)n, nb, solid, ph[PI_INV_SH], dh);
+                for (int i = 0; i < QP; ++i)
+                    ro.pops[(int64_t)i * N + n] = (double)(T(wp<QP>(i)) * ph[PI_HREF] + dh[i]);
             }
         }
         if (DIAG && diag) {
@@ -760,17 +767,17 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
             const T ign = theta / (gnorm + ph[PI_EPS]);   // theta n = theta grad / (|grad| + eps)
             st.tn[0] = st.grad[0] * ign; st.tn[1] = st.grad[1] * ign; st.tn[2] = st.grad[2] * ign;
             const T href = ph[PI_HREF];
-            T B[QH];
-            if (MODE == MODE_STEP) read_pops<T, SH, QH, PAR>(hb, (uint32_t)n, nb, solid, ph[PI_INV_SH], B);
+            T B[QP];
+            if (MODE == MODE_STEP) read_pops<T, SH, QP, PAR>(hb, (uint32_t)n, nb, solid, ph[PI_INV_SH], B);
             const T itau_h = ph[PI_ITAU_H];
             {
-                const T heq0 = T(wh(0)) * ((pc - href) + pc * (-T(2) * st.uu));
+                const T heq0 = T(wp<QP>(0)) * ((pc - href) + pc * (-T(i2tp<QP>()) * st.uu));
                 B[0] = MODE == MODE_STEP ? B[0] + (heq0 - B[0]) * itau_h : heq0;
             }
 #pragma unroll
-            for (int i = 1; i < QH; i += 2) {
+            for (int i = 1; i < QP; i += 2) {
                 T hp, hm;
-                h_eq_pair<T>(i, st, href, hp, hm);
+                h_eq_pair<T, QP>(i, st, href, hp, hm);
                 if (MODE == MODE_STEP) {
                     B[i] = B[i] + (hp - B[i]) * itau_h;
                     B[i + 1] = B[i + 1] + (hm - B[i + 1]) * itau_h;
@@ -779,8 +786,8 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
                     B[i + 1] = hm;
                 }
             }
-            if (MODE == MODE_STEP) write_pops<T, SH, QH, PAR>(hb, (uint32_t)n, nb, solid, ph[PI_SH], B);
-            else place_pops<T, SH, QH, PAR>(hb, (uint32_t)n, nb, solid, ph[PI_SH], B);
+            if (MODE == MODE_STEP) write_pops<T, SH, QP, PAR>(hb, (uint32_t)n, nb, solid, ph[PI_SH], B);
+            else place_pops<T, SH, QP, PAR>(hb, (uint32_t)n, nb, solid, ph[PI_SH], B);
         }
 
         // ---- solid links (Sec. III.A).  Half-way bounce-back returns the
@@ -913,7 +920,7 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
 // --------------------------------------------------------------- restore
 // Populations f_i(x) of a step of parity PAR (canonical [26][N] doubles) into
 // the AA slots that step reads.
-template <typename T, typename SH, typename SG, int PAR>
+template <typename T, typename SH, typename SG, int PAR, int QP>
 __global__ void __launch_bounds__(NTHREADS)
 restore_kernel(const Desc* __restrict__ descs, const Tile* __restrict__ tiles,
                const double* __restrict__ pops) {
@@ -926,7 +933,7 @@ restore_kernel(const Desc* __restrict__ descs, const Tile* __restrict__ tiles,
     Phys<T> ph;
     ph.load(D);
     const int64_t N = uni(D->N);
-    const PopArray<SH, QH> hb = pop_array<SH, QH>(D->h, uni(D->N));
+    const PopArray<SH, QP> hb = pop_array<SH, QP>(D->h, uni(D->N));
     const PopArray<SG, QG> gb = pop_array<SG, QG>(D->g, uni(D->N));
     const uint8_t* __restrict__ flg = unip(D->flag);
     const uint32_t* __restrict__ lnk = unip(D->link);
@@ -938,10 +945,10 @@ restore_kernel(const Desc* __restrict__ descs, const Tile* __restrict__ tiles,
         const uint32_t solid = (f & F_NEAR_WALL) ? (lnk[n] & SOLID_MASK) : 0u;
         Nbr nb;
         nb.init(x, y, z, nx, ny, nz);
-        T dh[QH], dg[QG];
-        for (int i = 0; i < QH; ++i) dh[i] = (T)(pops[(int64_t)i * N + n] - wh(i) * D->href);
-        for (int i = 0; i < QG; ++i) dg[i] = (T)(pops[(int64_t)(QH + i) * N + n] - wg(i) * D->gref);
-        place_pops<T, SH, QH, PAR>(hb, (uint32_t)n, nb, solid, ph[PI_SH], dh);
+        T dh[QP], dg[QG];
+        for (int i = 0; i < QP; ++i) dh[i] = (T)(pops[(int64_t)i * N + n] - wp<QP>(i) * D->href);
+        for (int i = 0; i < QG; ++i) dg[i] = (T)(pops[(int64_t)(QP + i) * N + n] - wg(i) * D->gref);
+        place_pops<T, SH, QP, PAR>(hb, (uint32_t)n, nb, solid, ph[PI_SH], dh);
         place_pops<T, SG, QG, PAR>(gb, (uint32_t)n, nb, solid, ph[PI_SG], dg);
     }
 }
@@ -954,7 +961,7 @@ restore_kernel(const Desc* __restrict__ descs, const Tile* __restrict__ tiles,
 // that point into a fluid node are written, into the slots the next step's
 // parity reads: (g + c_i, i) for an even step, (g, opp(i)) for an odd one.
 // Runs after the sweep of step t and before the step counter advances.
-template <typename T, typename SH, typename SG>
+template <typename T, typename SH, typename SG, int QP>
 __global__ void __launch_bounds__(NTHREADS)
 ghost_kernel(const Desc* __restrict__ descs, const GhostRef* __restrict__ ghosts, int nghosts) {
     const int k = blockIdx.x * NTHREADS + threadIdx.x;
@@ -984,7 +991,8 @@ ghost_kernel(const Desc* __restrict__ descs, const GhostRef* __restrict__ ghosts
     const T rho = pp[PI_RHO_G] + pb * pp[PI_RDIF];
     const double Pb = D->face_P[face] + D->face_ramp[face] * (double)(next - D->t0);
     const T pdb = (T)(Pb * 3.0) - pp[PI_GREF];
-    const T iTg = T(3), i2Tg = T(1.5), i2Tg2 = T(4.5), iTh = T(4), i2Th = T(2), i2Th2 = T(8);
+    const T iTg = T(3), i2Tg = T(1.5), i2Tg2 = T(4.5);
+    const T iTh = T(itp<QP>()), i2Th = T(i2tp<QP>()), i2Th2 = T(i2tp2<QP>());
     Nbr nb;
     nb.init(x, y, z, nx, ny, nz);
     // a launch may mix lattices, so the per-direction bases are per lane here
@@ -1001,37 +1009,40 @@ ghost_kernel(const Desc* __restrict__ descs, const GhostRef* __restrict__ ghosts
         const T gam = cu * iTg + cu * cu * i2Tg2 - uu * i2Tg;
         const T vg = T(wg(i)) * (rho * gam + pdb);
         gq[q][dst] = (SG)(Store<SG>::scaled ? vg * pp[PI_SG] : vg);
-        if (i < QH) {
+        if (i < QP) {
             const T gh = cu * iTh + cu * cu * i2Th2 - uu * i2Th;
-            const T vh = T(wh(i)) * ((pc - pp[PI_HREF]) + pc * gh);
+            const T vh = T(wp<QP>(i)) * ((pc - pp[PI_HREF]) + pc * gh);
             hq[q][dst] = (SH)(Store<SH>::scaled ? vh * pp[PI_SH] : vh);
         }
     }
 }
 
+
+// -------------------------------------------------------------- launchers
 template <typename T, typename SH, typename SG>
-hipError_t launch_ghosts_storage(const Desc* d, const GhostRef* ghosts, int nghosts, hipStream_t s) {
+hipError_t launch_ghosts_storage(int qp, const Desc* d, const GhostRef* ghosts, int nghosts,
+                                 hipStream_t s) {
     if (nghosts <= 0) return hipSuccess;
     dim3 grid((nghosts + NTHREADS - 1) / NTHREADS), block(NTHREADS);
-    ghost_kernel<T, SH, SG><<<grid, block, 0, s>>>(d, ghosts, nghosts);
+    if (qp == 19) ghost_kernel<T, SH, SG, 19><<<grid, block, 0, s>>>(d, ghosts, nghosts);
+    else ghost_kernel<T, SH, SG, QH><<<grid, block, 0, s>>>(d, ghosts, nghosts);
     return hipGetLastError();
 }
 
-// -------------------------------------------------------------- launchers
-template <typename T, typename SH, typename SG, int TX, int PAR>
+template <typename T, typename SH, typename SG, int TX, int PAR, int QP>
 hipError_t launch_sweep_tp(int mode, Desc* d, const Tile* tiles, int ntiles, int diag,
                            ReadOut ro, InitIn in, hipStream_t s) {
     dim3 grid(ntiles), block(NTHREADS);
     switch (mode) {
         case MODE_STEP:
-            if (diag) sweep_kernel<T, SH, SG, MODE_STEP, true, TX, PAR><<<grid, block, 0, s>>>(d, tiles, ro, in);
-            else sweep_kernel<T, SH, SG, MODE_STEP, false, TX, PAR><<<grid, block, 0, s>>>(d, tiles, ro, in);
+            if (diag) sweep_kernel<T, SH, SG, MODE_STEP, true, TX, PAR, QP><<<grid, block, 0, s>>>(d, tiles, ro, in);
+            else sweep_kernel<T, SH, SG, MODE_STEP, false, TX, PAR, QP><<<grid, block, 0, s>>>(d, tiles, ro, in);
             break;
         case MODE_READ:
-            sweep_kernel<T, SH, SG, MODE_READ, true, TX, PAR><<<grid, block, 0, s>>>(d, tiles, ro, in);
+            sweep_kernel<T, SH, SG, MODE_READ, true, TX, PAR, QP><<<grid, block, 0, s>>>(d, tiles, ro, in);
             break;
         case MODE_INIT:
-            sweep_kernel<T, SH, SG, MODE_INIT, false, TX, PAR><<<grid, block, 0, s>>>(d, tiles, ro, in);
+            sweep_kernel<T, SH, SG, MODE_INIT, false, TX, PAR, QP><<<grid, block, 0, s>>>(d, tiles, ro, in);
             break;
         default:
             return hipErrorInvalidValue;
@@ -1039,39 +1050,56 @@ hipError_t launch_sweep_tp(int mode, Desc* d, const Tile* tiles, int ntiles, int
     return hipGetLastError();
 }
 
-template <typename T, typename SH, typename SG>
-hipError_t launch_sweep_storage(int mode, int tx, int parity, Desc* d, const Tile* tiles,
-                                int ntiles, int diag, ReadOut ro, InitIn in, hipStream_t s) {
-    if (ntiles <= 0) return hipSuccess;
+template <typename T, typename SH, typename SG, int QP>
+hipError_t launch_sweep_q(int mode, int tx, int parity, Desc* d, const Tile* tiles, int ntiles,
+                          int diag, ReadOut ro, InitIn in, hipStream_t s) {
     const int key = tx * 2 + (parity & 1);
     switch (key) {
-        case 128: return launch_sweep_tp<T, SH, SG, 64, 0>(mode, d, tiles, ntiles, diag, ro, in, s);
-        case 129: return launch_sweep_tp<T, SH, SG, 64, 1>(mode, d, tiles, ntiles, diag, ro, in, s);
-        case 64: return launch_sweep_tp<T, SH, SG, 32, 0>(mode, d, tiles, ntiles, diag, ro, in, s);
-        case 65: return launch_sweep_tp<T, SH, SG, 32, 1>(mode, d, tiles, ntiles, diag, ro, in, s);
-        case 32: return launch_sweep_tp<T, SH, SG, 16, 0>(mode, d, tiles, ntiles, diag, ro, in, s);
-        case 33: return launch_sweep_tp<T, SH, SG, 16, 1>(mode, d, tiles, ntiles, diag, ro, in, s);
+        case 128: return launch_sweep_tp<T, SH, SG, 64, 0, QP>(mode, d, tiles, ntiles, diag, ro, in, s);
+        case 129: return launch_sweep_tp<T, SH, SG, 64, 1, QP>(mode, d, tiles, ntiles, diag, ro, in, s);
+        case 64: return launch_sweep_tp<T, SH, SG, 32, 0, QP>(mode, d, tiles, ntiles, diag, ro, in, s);
+        case 65: return launch_sweep_tp<T, SH, SG, 32, 1, QP>(mode, d, tiles, ntiles, diag, ro, in, s);
+        case 32: return launch_sweep_tp<T, SH, SG, 16, 0, QP>(mode, d, tiles, ntiles, diag, ro, in, s);
+        case 33: return launch_sweep_tp<T, SH, SG, 16, 1, QP>(mode, d, tiles, ntiles, diag, ro, in, s);
     }
     return hipErrorInvalidValue;
 }
 
+template <typename T, typename SH, typename SG>
+hipError_t launch_sweep_storage(int qp, int mode, int tx, int parity, Desc* d, const Tile* tiles,
+                                int ntiles, int diag, ReadOut ro, InitIn in, hipStream_t s) {
+    if (ntiles <= 0) return hipSuccess;
+    if (qp == 19) return launch_sweep_q<T, SH, SG, 19>(mode, tx, parity, d, tiles, ntiles, diag, ro, in, s);
+    return launch_sweep_q<T, SH, SG, QH>(mode, tx, parity, d, tiles, ntiles, diag, ro, in, s);
+}
+
 template <typename T, typename SH>
-hipError_t launch_phi_storage(int parity, const Desc* d, const Tile* tiles, int ntiles,
+hipError_t launch_phi_storage(int qp, int parity, const Desc* d, const Tile* tiles, int ntiles,
                               hipStream_t s, int force) {
     if (ntiles <= 0) return hipSuccess;
     dim3 grid(ntiles), block(NTHREADS);
-    if (parity & 1) phi_kernel<T, SH, 1><<<grid, block, 0, s>>>(d, tiles, force);
-    else phi_kernel<T, SH, 0><<<grid, block, 0, s>>>(d, tiles, force);
+    const int key = (qp == 19 ? 2 : 0) + (parity & 1);
+    switch (key) {
+        case 0: phi_kernel<T, SH, 0, QH><<<grid, block, 0, s>>>(d, tiles, force); break;
+        case 1: phi_kernel<T, SH, 1, QH><<<grid, block, 0, s>>>(d, tiles, force); break;
+        case 2: phi_kernel<T, SH, 0, 19><<<grid, block, 0, s>>>(d, tiles, force); break;
+        default: phi_kernel<T, SH, 1, 19><<<grid, block, 0, s>>>(d, tiles, force); break;
+    }
     return hipGetLastError();
 }
 
 template <typename T, typename SH, typename SG>
-hipError_t launch_restore_storage(int parity, const Desc* d, const Tile* tiles, int ntiles,
+hipError_t launch_restore_storage(int qp, int parity, const Desc* d, const Tile* tiles, int ntiles,
                                   const double* pops, hipStream_t s) {
     if (ntiles <= 0) return hipSuccess;
     dim3 grid(ntiles), block(NTHREADS);
-    if (parity & 1) restore_kernel<T, SH, SG, 1><<<grid, block, 0, s>>>(d, tiles, pops);
-    else restore_kernel<T, SH, SG, 0><<<grid, block, 0, s>>>(d, tiles, pops);
+    const int key = (qp == 19 ? 2 : 0) + (parity & 1);
+    switch (key) {
+        case 0: restore_kernel<T, SH, SG, 0, QH><<<grid, block, 0, s>>>(d, tiles, pops); break;
+        case 1: restore_kernel<T, SH, SG, 1, QH><<<grid, block, 0, s>>>(d, tiles, pops); break;
+        case 2: restore_kernel<T, SH, SG, 0, 19><<<grid, block, 0, s>>>(d, tiles, pops); break;
+        default: restore_kernel<T, SH, SG, 1, 19><<<grid, block, 0, s>>>(d, tiles, pops); break;
+    }
     return hipGetLastError();
 }
 

@@ -63,6 +63,10 @@ int validate_params(const lbm_params* p, const lbm_geometry* geo) {
             return LBM_E_INVAL;
         }
     }
+    if (p->q_phase != 0 && p->q_phase != 7 && p->q_phase != 19) {
+        set_error("q_phase %d: the phase lattice is D3Q7 (7) or D3Q19 (19)", p->q_phase);
+        return LBM_E_INVAL;
+    }
     if (p->hysteresis && !(p->hyst_beta >= 0.0 && p->hyst_beta < 1.0)) {
         set_error("hyst_beta %g outside [0, 1)", p->hyst_beta);
         return LBM_E_INVAL;
@@ -143,7 +147,7 @@ static void layout_offsets(const lbm_params* p, int64_t ntiles, int64_t nghosts,
     size_t o = 0;
     L->off_desc = o; o = align256(o + sizeof(Desc));
     L->off_counter = o; o = align256(o + sizeof(unsigned int));
-    L->off_h = o; o = align256(o + (size_t)QH * N * sh);
+    L->off_h = o; o = align256(o + (size_t)phase_q(p) * N * sh);
     L->off_g = o; o = align256(o + (size_t)QG * N * sg);
     L->off_phi = o; o = align256(o + (size_t)N * sphi);
     L->off_flag = o; o = align256(o + (size_t)N);
@@ -292,7 +296,8 @@ void fill_desc(const lbm_params* p, const lbm_geometry* geo, const LatticeLayout
     {
         int sh, sg, sphi;
         storage_sizes(p->storage, &sh, &sg, &sphi);
-        for (int q = 0; q < QH; ++q) d->hq[q] = base + L.off_h + (size_t)q * L.N * sh;
+        for (int q = 0; q < phase_q(p); ++q) d->hq[q] = base + L.off_h + (size_t)q * L.N * sh;
+        for (int q = phase_q(p); q < QHMAX; ++q) d->hq[q] = nullptr;
         for (int q = 0; q < QG; ++q) d->gq[q] = base + L.off_g + (size_t)q * L.N * sg;
     }
     d->phi = base + L.off_phi;
@@ -300,6 +305,7 @@ void fill_desc(const lbm_params* p, const lbm_geometry* geo, const LatticeLayout
     d->link = (const uint32_t*)(base + L.off_link);
     d->partials = (double*)(base + L.off_partials);
     d->gbuf = base + L.off_gbuf;
+    d->q_phase = phase_q(p);
     d->hysteresis = p->hysteresis ? 1 : 0;
     d->hyst_reset = 0;
     d->n_wall = p->hysteresis ? L.n_wall : 0;
@@ -344,7 +350,7 @@ void fill_desc(const lbm_params* p, const lbm_geometry* geo, const LatticeLayout
     d->u_max = p->u_max;
     // derived constants (Eq. 4 theta coefficient, Eq. 5 correction factor,
     // Eq. 9 chemical-potential coefficients, Eqs. 10-12 relaxation times)
-    const double TG = 1.0 / 3.0, TH = 0.25;
+    const double TG = 1.0 / 3.0, TH = phase_q(p) == 19 ? 1.0 / 3.0 : 0.25;
     double v[PI_COUNT];
     v[PI_RHO_G] = p->rho_g;
     v[PI_RDIF] = p->rho_l - p->rho_g;
@@ -398,7 +404,7 @@ int upload_and_init(const lbm_params* p, const lbm_geometry* geo, const lbm_init
     int sh, sg, sphi;
     storage_sizes(p->storage, &sh, &sg, &sphi);
     // zero populations and phi (solid slots stay zero), upload geometry
-    HIPCHK(hipMemsetAsync(base + L.off_h, 0, (size_t)QH * N * sh, s));
+    HIPCHK(hipMemsetAsync(base + L.off_h, 0, (size_t)phase_q(p) * N * sh, s));
     HIPCHK(hipMemsetAsync(base + L.off_g, 0, (size_t)QG * N * sg, s));
     HIPCHK(hipMemsetAsync(base + L.off_counter, 0, sizeof(unsigned int), s));
     HIPCHK(hipMemsetAsync(base + L.off_partials, 0, L.tiles.size() * NPART * sizeof(double), s));
@@ -423,10 +429,10 @@ int upload_and_init(const lbm_params* p, const lbm_geometry* geo, const lbm_init
     if (init->kind == LBM_INIT_POPULATIONS) {
         if (!init->pops) { set_error("POPULATIONS init needs pops"); return LBM_E_INVAL; }
         double* dpops = nullptr;
-        HIPCHK(hipMalloc(&dpops, (size_t)(QH + QG) * N * sizeof(double)));
-        hipError_t e = hipMemcpyAsync(dpops, init->pops, (size_t)(QH + QG) * N * sizeof(double),
+        HIPCHK(hipMalloc(&dpops, (size_t)(phase_q(p) + QG) * N * sizeof(double)));
+        hipError_t e = hipMemcpyAsync(dpops, init->pops, (size_t)(phase_q(p) + QG) * N * sizeof(double),
                                       hipMemcpyHostToDevice, s);
-        if (e == hipSuccess) e = launch_restore(p->storage, (int)(step0 & 1), ddesc, dtiles, nt, dpops, s);
+        if (e == hipSuccess) e = launch_restore(p->storage, phase_q(p), (int)(step0 & 1), ddesc, dtiles, nt, dpops, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         hipFree(dpops);
         if (e != hipSuccess) { set_error("restore: %s", hipGetErrorString(e)); return LBM_E_DEVICE; }
@@ -475,7 +481,7 @@ int upload_and_init(const lbm_params* p, const lbm_geometry* geo, const lbm_init
     }
     ReadOut ro = {nullptr, nullptr, nullptr, nullptr};
     InitIn in = {du, dP};
-    hipError_t e = launch_sweep(p->storage, MODE_INIT, L.tx, 0, ddesc, dtiles, nt, 0, ro, in, s);
+    hipError_t e = launch_sweep(p->storage, phase_q(p), MODE_INIT, L.tx, 0, ddesc, dtiles, nt, 0, ro, in, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (du) hipFree(du);
     if (dP) hipFree(dP);
@@ -493,7 +499,8 @@ int read_lattice(int storage, const Desc& hdesc, int parity, Desc* d_desc, const
     const size_t o_phi = nd; if (phi && (mask & LBM_PHI)) nd += N;
     const size_t o_P = nd; if (P && (mask & LBM_P)) nd += N;
     const size_t o_u = nd; if (u && (mask & LBM_U)) nd += 3 * N;
-    const size_t o_pop = nd; if (want_pop) nd += (size_t)(QH + QG) * N;
+    const int qh = hdesc.q_phase == 19 ? 19 : 7;
+    const size_t o_pop = nd; if (want_pop) nd += (size_t)(qh + QG) * N;
     if (nd) HIPCHK(hipMalloc(&buf, nd * sizeof(double)));
     ReadOut ro;
     ro.phi = (phi && (mask & LBM_PHI)) ? buf + o_phi : nullptr;
@@ -501,19 +508,19 @@ int read_lattice(int storage, const Desc& hdesc, int parity, Desc* d_desc, const
     ro.u = (u && (mask & LBM_U)) ? buf + o_u : nullptr;
     ro.pops = want_pop ? buf + o_pop : nullptr;
     InitIn in = {nullptr, nullptr};
-    hipError_t e = launch_phi(storage, parity, d_desc, d_tiles, ntiles, s, 1);
-    if (e == hipSuccess) e = launch_sweep(storage, MODE_READ, hdesc.tx, parity, d_desc, d_tiles, ntiles, 1, ro, in, s);
+    hipError_t e = launch_phi(storage, qh, parity, d_desc, d_tiles, ntiles, s, 1);
+    if (e == hipSuccess) e = launch_sweep(storage, qh, MODE_READ, hdesc.tx, parity, d_desc, d_tiles, ntiles, 1, ro, in, s);
     if (e == hipSuccess && ro.phi) e = hipMemcpyAsync(phi, ro.phi, N * sizeof(double), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess && ro.P) e = hipMemcpyAsync(P, ro.P, N * sizeof(double), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess && ro.u) e = hipMemcpyAsync(u, ro.u, 3 * N * sizeof(double), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess && ro.pops) {
         double* dst = pops;
         if (mask & LBM_POP_H) {
-            e = hipMemcpyAsync(dst, ro.pops, (size_t)QH * N * sizeof(double), hipMemcpyDeviceToHost, s);
-            dst += (size_t)QH * N;
+            e = hipMemcpyAsync(dst, ro.pops, (size_t)qh * N * sizeof(double), hipMemcpyDeviceToHost, s);
+            dst += (size_t)qh * N;
         }
         if (e == hipSuccess && (mask & LBM_POP_G))
-            e = hipMemcpyAsync(dst, ro.pops + (size_t)QH * N, (size_t)QG * N * sizeof(double),
+            e = hipMemcpyAsync(dst, ro.pops + (size_t)qh * N, (size_t)QG * N * sizeof(double),
                                hipMemcpyDeviceToHost, s);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);

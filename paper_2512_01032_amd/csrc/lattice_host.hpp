@@ -40,6 +40,9 @@ int validate_params(const lbm_params* p, const lbm_geometry* geo);
 int choose_tx(int nx);
 int choose_tz(const lbm_params* p, int tx);
 
+// Size of the phase-field lattice (7 or 19).
+inline int phase_q(const lbm_params* p) { return p->q_phase == 19 ? 19 : 7; }
+
 // Bytes per stored population of each lattice.
 void storage_sizes(int storage, int* sh, int* sg, int* sphi);
 

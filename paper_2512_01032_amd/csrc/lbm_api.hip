@@ -153,6 +153,7 @@ extern "C" int lbm_step(lbm_handle* h, int64_t nsteps) {
     if (rc != LBM_OK) return rc;
     HIPRET(hipSetDevice(h->device));
     const int storage = h->p.storage;
+    const int qp = phase_q(&h->p);
     const ReadOut ro = {nullptr, nullptr, nullptr, nullptr};
     const InitIn in = {nullptr, nullptr};
     const int64_t de = h->p.diag_every > 0 ? h->p.diag_every : 0;
@@ -168,12 +169,12 @@ extern "C" int lbm_step(lbm_handle* h, int64_t nsteps) {
             HIPRET(hipEventRecord(e0, h->stream));
         }
         const int par = (int)(t & 1);
-        HIPRET(launch_phi(storage, par, h->ddesc, h->dtiles, h->ntiles, h->stream));
+        HIPRET(launch_phi(storage, qp, par, h->ddesc, h->dtiles, h->ntiles, h->stream));
         if (h->timing) HIPRET(hipEventRecord(e1, h->stream));
-        HIPRET(launch_sweep(storage, MODE_STEP, h->L.tx, par, h->ddesc, h->dtiles, h->ntiles, diag, ro, in,
+        HIPRET(launch_sweep(storage, qp, MODE_STEP, h->L.tx, par, h->ddesc, h->dtiles, h->ntiles, diag, ro, in,
                             h->stream));
         if (h->nghosts)
-            HIPRET(launch_ghosts(storage, h->ddesc, h->dghosts, h->nghosts, h->stream));
+            HIPRET(launch_ghosts(storage, qp, h->ddesc, h->dghosts, h->nghosts, h->stream));
         HIPRET(launch_advance(h->ddesc, 1, h->stream));
         if (h->timing) HIPRET(hipEventRecord(e2, h->stream));
     }
@@ -270,6 +271,6 @@ extern "C" int lbm_get_info(const lbm_handle* h, lbm_info* info) {
     info->footprint = h->L.total;
     int sh, sg, sphi;
     storage_sizes(h->p.storage, &sh, &sg, &sphi);
-    info->bytes_per_fluid_update = 2.0 * (QH * sh + QG * sg);
+    info->bytes_per_fluid_update = 2.0 * (phase_q(&h->p) * sh + QG * sg);
     return LBM_OK;
 }

@@ -17,7 +17,8 @@
 
 namespace pflbm {
 
-constexpr int QH = 7;
+constexpr int QH = 7;        // D3Q7 phase lattice (the default)
+constexpr int QHMAX = 19;    // D3Q19 phase lattice (q_phase = 19)
 constexpr int QG = 19;
 constexpr int NTHREADS = 256;       // threads per tile / workgroup
 constexpr int NPART = 10;           // FP64 diagnostic partials per tile
@@ -56,9 +57,11 @@ struct alignas(256) Desc {
     int64_t N;
     int32_t storage;
     int32_t ntiles;                // tiles of this lattice
+    int32_t q_phase;               // phase lattice: 7 or 19
+    int32_t pad_q;
     void* h;
     void* g;
-    void* hq[7];                   // h + q N: base of each direction
+    void* hq[QHMAX];               // h + q N: base of each phase direction
     void* gq[19];
     void* phi;
     const uint8_t* flag;
@@ -146,19 +149,21 @@ struct InitIn {                // device inputs of MODE_INIT
     const double* P;           // [N] or NULL
 };
 
-// host-side launchers (kernels.hip).  parity: AA parity of the step every
-// lattice in the table is at; tx: tile width of every tile (16, 32 or 64).
+// host-side launchers (kernels.hip).  qp: phase-lattice size (7 or 19) of
+// every lattice in the table; parity: AA parity of the step every lattice
+// in the table is at; tx: tile width of every tile (16, 32 or 64).
 // force: run the phi pass even for lattices past their stop step (read-back).
-hipError_t launch_phi(int storage, int parity, const Desc* d, const Tile* tiles, int ntiles,
+hipError_t launch_phi(int storage, int qp, int parity, const Desc* d, const Tile* tiles, int ntiles,
                       hipStream_t s, int force = 0);
-hipError_t launch_sweep(int storage, int mode, int tx, int parity, Desc* d, const Tile* tiles,
+hipError_t launch_sweep(int storage, int qp, int mode, int tx, int parity, Desc* d, const Tile* tiles,
                         int ntiles, int diag, ReadOut ro, InitIn in, hipStream_t s);
-hipError_t launch_restore(int storage, int parity, const Desc* d, const Tile* tiles, int ntiles,
+hipError_t launch_restore(int storage, int qp, int parity, const Desc* d, const Tile* tiles, int ntiles,
                           const double* pops, hipStream_t s);
-// after a sweep: equilibrium populations of every listed pressure ghost for
-// the next step (the step counter the sweep advanced), from its owner's u
+// step counter of every lattice in the table: t -> t+1 unless stopped
 hipError_t launch_advance(Desc* d, int nlat, hipStream_t s);
-hipError_t launch_ghosts(int storage, const Desc* d, const GhostRef* ghosts, int nghosts,
+// after a sweep, before the step advances: equilibrium populations of every
+// listed pressure ghost for the next step, from its owner's phi and u
+hipError_t launch_ghosts(int storage, int qp, const Desc* d, const GhostRef* ghosts, int nghosts,
                          hipStream_t s);
 
 }  // namespace pflbm

@@ -119,8 +119,10 @@ struct lbm_server {
     size_t tiles_cap = 0;
     GhostRef* dghosts = nullptr;
     size_t ghosts_cap = 0;
-    struct Group { int tx, off, n; };
-    std::vector<Group> groups;
+    struct Group { int qp, tx, off, n; };
+    std::vector<Group> groups;         // sweep launches: one per (phase lattice, tile width)
+    std::vector<Group> phi_groups;     // phi launches: one per phase lattice (tx unused)
+    std::vector<Group> ghost_groups;   // ghost launches: one per phase lattice (tx unused)
     int ntiles = 0, nghosts = 0, table_slots = 0;
     int64_t resident_nodes = 0;
     bool dirty = true;
@@ -238,24 +240,36 @@ int admit_one(lbm_server* s) {
     return 1;
 }
 
-// Concatenated tile tables of all resident lattices, grouped by tile width.
+// Concatenated tile tables of all resident lattices, grouped by phase
+// lattice and, within it, by tile width (each kernel instance handles one
+// of each); ghost tables grouped by phase lattice.
 int rebuild_tables(lbm_server* s) {
     std::vector<Tile> tiles;
     std::vector<GhostRef> ghosts;
     s->groups.clear();
+    s->phi_groups.clear();
+    s->ghost_groups.clear();
     s->table_slots = 0;
-    for (int tx : {64, 32, 16}) {
-        const int off = (int)tiles.size();
-        for (auto& j : s->active) {
-            if (j->L.tx != tx) continue;
-            for (Tile t : j->L.tiles) { t.lat = j->slot; tiles.push_back(t); }
+    for (int qp : {7, 19}) {
+        const int qoff = (int)tiles.size();
+        for (int tx : {64, 32, 16}) {
+            const int off = (int)tiles.size();
+            for (auto& j : s->active) {
+                if (j->L.tx != tx || phase_q(&j->p) != qp) continue;
+                for (Tile t : j->L.tiles) { t.lat = j->slot; tiles.push_back(t); }
+            }
+            if ((int)tiles.size() > off) s->groups.push_back({qp, tx, off, (int)tiles.size() - off});
         }
-        if ((int)tiles.size() > off) s->groups.push_back({tx, off, (int)tiles.size() - off});
+        if ((int)tiles.size() > qoff) s->phi_groups.push_back({qp, 0, qoff, (int)tiles.size() - qoff});
+        const int goff = (int)ghosts.size();
+        for (auto& j : s->active) {
+            if (phase_q(&j->p) != qp) continue;
+            for (GhostRef g : j->L.ghosts) { g.lat = j->slot; ghosts.push_back(g); }
+        }
+        if ((int)ghosts.size() > goff)
+            s->ghost_groups.push_back({qp, 0, goff, (int)ghosts.size() - goff});
     }
-    for (auto& j : s->active) {
-        for (GhostRef g : j->L.ghosts) { g.lat = j->slot; ghosts.push_back(g); }
-        s->table_slots = std::max(s->table_slots, j->slot + 1);
-    }
+    for (auto& j : s->active) s->table_slots = std::max(s->table_slots, j->slot + 1);
     if (tiles.size() > s->tiles_cap) {
         if (s->dtiles) SRV_CHK(hipFree(s->dtiles));
         s->dtiles = nullptr;
@@ -289,13 +303,17 @@ hipError_t enqueue_steps(lbm_server* s) {
     const InitIn in = {nullptr, nullptr};
     for (int k = 0; k < s->interval; ++k) {
         const int par = k & 1;
-        hipError_t e = launch_phi(storage, par, s->dtable, s->dtiles, s->ntiles, s->stream, 0);
+        hipError_t e = hipSuccess;
+        for (const auto& g : s->phi_groups)
+            if (e == hipSuccess)
+                e = launch_phi(storage, g.qp, par, s->dtable, s->dtiles + g.off, g.n, s->stream, 0);
         for (const auto& g : s->groups)
             if (e == hipSuccess)
-                e = launch_sweep(storage, MODE_STEP, g.tx, par, s->dtable, s->dtiles + g.off, g.n, 0,
-                                 ro, in, s->stream);
-        if (e == hipSuccess && s->nghosts)
-            e = launch_ghosts(storage, s->dtable, s->dghosts, s->nghosts, s->stream);
+                e = launch_sweep(storage, g.qp, MODE_STEP, g.tx, par, s->dtable, s->dtiles + g.off, g.n,
+                                 0, ro, in, s->stream);
+        for (const auto& g : s->ghost_groups)
+            if (e == hipSuccess)
+                e = launch_ghosts(storage, g.qp, s->dtable, s->dghosts + g.off, g.n, s->stream);
         if (e == hipSuccess) e = launch_advance(s->dtable, s->table_slots, s->stream);
         if (e != hipSuccess) return e;
     }

@@ -42,7 +42,7 @@ class lbm_params(ctypes.Structure):
         ("face_bc", c_int32 * 6), ("face_P", c_double * 6), ("face_ramp", c_double * 6),
         ("diag_every", c_int32), ("u_max", c_double),
         ("fp16_log2_scale_h", c_int32), ("fp16_log2_scale_g", c_int32),
-        ("hysteresis", c_int32), ("hyst_beta", c_double),
+        ("hysteresis", c_int32), ("hyst_beta", c_double), ("q_phase", c_int32),
     ]
 
 
@@ -189,6 +189,7 @@ def params_from_workload(wl, storage=None, diag_every=0, u_max=0.0):
     p.u_max = float(u_max)
     p.hysteresis = 1 if getattr(ph, "hysteresis", False) else 0
     p.hyst_beta = float(getattr(ph, "hyst_beta", 0.0))
+    p.q_phase = int(getattr(ph, "q_phase", 7))
     return p
 
 
@@ -264,9 +265,10 @@ class Lattice:
         return phi, P, u
 
     def pops(self):
-        buf = np.zeros((26,) + self.shape)
+        qh = self.params.q_phase if self.params.q_phase else 7
+        buf = np.zeros((qh + 19,) + self.shape)
         check(lbm_read_fields(self.h, LBM_POP_H | LBM_POP_G, None, None, None, buf.ctypes.data))
-        return buf[:7], buf[7:]
+        return buf[:qh], buf[qh:]
 
     def diagnostics(self):
         d = lbm_diag()

@@ -130,3 +130,17 @@ def test_rejections_and_tickets():
     with pytest.raises(lbm.LbmError):
         srv.poll(12345)
     srv.close()
+
+
+def test_alone_equals_mix_bitwise_two_phase_lattices():
+    """Requests on the D3Q7 and the D3Q19 phase lattice batched together:
+    the server groups tiles and ghosts by lattice kind; each result is still
+    bitwise the request run alone."""
+    import dataclasses
+    lbm = _lbm()
+    wls = _mix()[:5]
+    for k in (1, 2, 4):
+        wls[k].phys = dataclasses.replace(wls[k].phys, q_phase=19)
+        wls[k].name += "_q19"
+    res = _serve(lbm, wls, hbm_budget=1 << 30, use_graph=True, ticks_per_sync=6)
+    _check_same(lbm, wls, res)

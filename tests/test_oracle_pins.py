@@ -442,3 +442,34 @@ def test_duct_coefficient_matches_paper():
     lines = [l for l in open(os.path.join(GOLDEN, "duct_coefficient.txt")) if not l.startswith("#")]
     ratio, value = (float(v) for v in lines[0].split())
     assert abs(theory.duct_resistance_coefficient(ratio) - value) <= 0.01
+
+
+def test_mobility_correction_sets_the_rounding_sensitivity():
+    """Conditioning of Eq. 5, which bounds what any FP32 evaluation can
+    reach: the correction ramps over D = 1e-4 next to phi = 0 and phi = 1,
+    so absolute phi noise of FP32 size (3e-8 per step, the resolution of
+    phi = 1/2 + sum of shifted deviations) is amplified a hundred-fold and
+    more when the correction is on, and barely at all when it is off.
+    Same input (D3Q19 phase lattice, walls, pressure faces, 40 steps) as the
+    GPU's reduced-precision D3Q19 test."""
+    out = {}
+    for mc in (True, False):
+        wl = I.random_small(40, 12, 10, seed=6, walls=True, open_x=True, optimised_model=True,
+                            u_amp=0.002)
+        wl.phys = dataclasses.replace(wl.phys, q_phase=19, mobility_corr=mc)
+        a = ref.Oracle(wl)
+        a.step(40)
+        b = ref.Oracle(wl)
+        fluid = b.kinds() == 0
+        rng = np.random.default_rng(2)
+        for t in range(40):
+            h, g = b.pops()
+            h = h.copy()
+            h[0] += np.where(fluid, 3e-8 * rng.uniform(-1.0, 1.0, h[0].shape), 0.0)
+            b.set_pops(h, g, t)
+            b.step(1)
+        pa, pb = a.fields()[0], b.fields()[0]
+        out[mc] = np.abs(pa - pb)[fluid].max() / np.abs(pa[fluid]).max()
+    print(out)
+    assert out[False] <= 1e-6
+    assert out[True] >= 100 * out[False]
