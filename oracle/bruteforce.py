@@ -132,8 +132,9 @@ class BruteForce:
 
     def _stencil(self, phi, hist_mode="eval"):
         """hist_mode (hysteresis only): "set" records the wall values,
-        "step" blends them with the recorded ones and records the result,
-        "eval" blends without recording."""
+        "step" blends them with the recorded ones and records the blend
+        (hysteresis 1) or the unblended value (hysteresis 2), "eval" blends
+        without recording."""
         ph = self.ph
         nb = np.zeros((19,) + self.shape)
         sol = np.zeros((19,) + self.shape, bool)
@@ -165,9 +166,11 @@ class BruteForce:
                 if hist_mode == "set":
                     self.hist[i] = np.where(sol[i], ps, self.hist[i])
                 else:
-                    ps = ph.hyst_beta * self.hist[i] + (1 - ph.hyst_beta) * ps
+                    fresh = ps
+                    ps = ph.hyst_beta * self.hist[i] + (1 - ph.hyst_beta) * fresh
                     if hist_mode == "step":
-                        self.hist[i] = np.where(sol[i], ps, self.hist[i])
+                        keep = fresh if int(ph.hysteresis) == 2 else ps
+                        self.hist[i] = np.where(sol[i], keep, self.hist[i])
             nb[i] = np.where(sol[i], ps, nb[i])
         grad = np.zeros((3,) + self.shape)
         lap = np.zeros(self.shape)

@@ -244,8 +244,12 @@ double lbmref_wet_phi_s(double phi_smpl, const double w[3], const int c[3], doub
 /* S2 + S3 at fluid node n: gradient and Laplacian of phi with the wetting
  * substitute at solid links. */
 /* What stencil() does with the hysteresis history of a node's wall links:
- * EVAL blends with it (read-out), STEP blends and stores the blended value
- * (a time step), SET stores the unblended value (initial state, restore). */
+ * EVAL blends with it (read-out), STEP blends and stores (a time step), SET
+ * stores the unblended value (initial state, restore).  What a step stores
+ * is the reading of the blend: the blended value it used (hysteresis = 1,
+ * the blend is recursive) or the unblended value from its own gradient
+ * (hysteresis = 2, a blend of the current and the previous step's
+ * gradient-derived values). */
 enum { HYST_EVAL = 0, HYST_STEP = 1, HYST_SET = 2 };
 
 static void stencil(lbmref_state *s, long n, double grad[3], double *lap, int hmode) {
@@ -279,8 +283,9 @@ static void stencil(lbmref_state *s, long n, double grad[3], double *lap, int hm
                 if (hmode == HYST_SET) {
                     *prev = ph[i];
                 } else {
-                    ph[i] = p->hyst_beta * (*prev) + (1.0 - p->hyst_beta) * ph[i];
-                    if (hmode == HYST_STEP) *prev = ph[i];
+                    const double fresh = ph[i];
+                    ph[i] = p->hyst_beta * (*prev) + (1.0 - p->hyst_beta) * fresh;
+                    if (hmode == HYST_STEP) *prev = p->hysteresis == 2 ? fresh : ph[i];
                 }
             }
         }

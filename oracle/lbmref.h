@@ -54,8 +54,10 @@ typedef struct lbmref_params {
     double theta_deg[16];  /* contact angle per solid material */
     double clamp_a;        /* a = 2 phi - 1 is clamped to [-1+clamp_a, 1-clamp_a] */
     /* contact-angle hysteresis (Sec. III.A): each wall link blends its value
-     * phi_s,i with the one it used at the previous step,
-     * phi_s,i = beta * previous + (1 - beta) * phi_s,i (current gradient) */
+     * with one kept from the previous step,
+     * phi_s,i = beta * previous + (1 - beta) * phi_s,i (current gradient);
+     * 0 off; 1: previous = the blended value that step used (recursive);
+     * 2: previous = the value from that step's own gradient */
     int hysteresis;
     double hyst_beta;
     /* phase-field lattice: 7 (D3Q7, T = 1/4) or 19 (D3Q19, T = 1/3, as the

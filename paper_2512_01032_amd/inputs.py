@@ -57,15 +57,18 @@ class Physics:
     slip_lo: float = 0.5
     slip_hi: float = 0.95
     P_ref: float = T_G
-    hysteresis: bool = False        # Sec. III.A: wall values blended with the previous step's
+    # Sec. III.A wall-value blend with the previous step: 0/False off; 1/True
+    # with the blended value that step used; 2 with that step's own
+    # gradient-derived value
+    hysteresis: int = 0
     hyst_beta: float = 0.95
     q_phase: int = 7                # phase-field lattice: 7 (D3Q7) or 19 (D3Q19, as in Sec. II.A)
 
 
-def optimised(ph: Physics, hysteresis: bool = False) -> Physics:
+def optimised(ph: Physics, hysteresis: int = 0) -> Physics:
     """The Sec. III.A model: tanh mixture switch and free slip in the band;
-    with hysteresis=True also the blend of each wall value with the one of
-    the previous step (factor hyst_beta)."""
+    with hysteresis 1 or 2 also the blend of each wall value with one kept
+    from the previous step (factor hyst_beta; see Physics.hysteresis)."""
     return dataclasses.replace(ph, mix_tanh=True, interface_slip=True, hysteresis=hysteresis)
 
 

@@ -28,8 +28,10 @@ def relmax(a, b):
 @pytest.mark.parametrize("kw,hyst,q", [(dict(), False, 7), (dict(walls=True), False, 7),
                                        (dict(walls=True, open_x=True), False, 7),
                                        (dict(walls=True, open_x=True, optimised_model=True), False, 7),
-                                       (dict(walls=True, open_x=True, optimised_model=True), True, 7),
-                                       (dict(walls=True, open_x=True, optimised_model=True), False, 19)])
+                                       (dict(walls=True, open_x=True, optimised_model=True), 1, 7),
+                                       (dict(walls=True, open_x=True, optimised_model=True), 2, 7),
+                                       (dict(walls=True, open_x=True, optimised_model=True), False, 19),
+                                       (dict(walls=True, open_x=True, optimised_model=True), 2, 19)])
 def test_bruteforce_reference_agrees(kw, hyst, q):
     """Whole-lattice NumPy transcription (np.roll streaming, masks) vs the
     node-by-node C oracle on a tiny lattice: pins indexing, periodic wrap,
@@ -376,13 +378,15 @@ def _cap_contact_line(phi_xz):
     return measure.crossings_1d(phi_xz[1])
 
 
-def test_hysteresis_with_zero_blend_is_no_hysteresis():
+@pytest.mark.parametrize("mode", [1, 2])
+def test_hysteresis_with_zero_blend_is_no_hysteresis(mode):
     """beta = 0 keeps no history (the blend returns the current value
-    exactly): identical to the model without hysteresis, bitwise."""
+    exactly): identical to the model without hysteresis, bitwise, in both
+    readings."""
     wl = I.random_small(10, 8, 9, seed=4, walls=True, open_x=True, optimised_model=True)
     a = ref.Oracle(wl)
     wl0 = I.random_small(10, 8, 9, seed=4, walls=True, open_x=True, optimised_model=True)
-    wl0.phys = dataclasses.replace(wl0.phys, hysteresis=True, hyst_beta=0.0)
+    wl0.phys = dataclasses.replace(wl0.phys, hysteresis=mode, hyst_beta=0.0)
     b = ref.Oracle(wl0)
     a.step(12)
     b.step(12)
@@ -391,33 +395,75 @@ def test_hysteresis_with_zero_blend_is_no_hysteresis():
     assert np.array_equal(ha, hb) and np.array_equal(ga, gb)
 
 
+def test_hysteresis_readings_part_at_the_third_step():
+    """The two readings of the blend keep different histories: the blended
+    value a step used (1) or that step's own gradient-derived value (2).
+    The history starts at the initial state's values, and the first step
+    sees that same state, so its blend returns the fresh value (to rounding:
+    0.95 x + 0.05 x) in both; the second step blends with the first step's
+    value, which is unblended in both; from the third step on the histories
+    differ.  Hence: equal to rounding after one and two steps (and the first
+    step equals the model without hysteresis), different after three."""
+    outs = {}
+    for mode in (1, 2):
+        wl = I.random_small(10, 8, 9, seed=4, walls=True, open_x=True, optimised_model=True)
+        wl.phys = dataclasses.replace(wl.phys, hysteresis=mode, hyst_beta=0.95)
+        o = ref.Oracle(wl)
+        seq = []
+        for _ in range(3):
+            o.step(1)
+            seq.append(np.concatenate(o.pops()))
+        outs[mode] = seq
+    plain = I.random_small(10, 8, 9, seed=4, walls=True, open_x=True, optimised_model=True)
+    p = ref.Oracle(plain)
+    p.step(1)
+    first_plain = np.concatenate(p.pops())
+    p.step(1)
+    second_plain = np.concatenate(p.pops())
+    d = [relmax(outs[1][k], outs[2][k]) for k in range(3)]
+    print("mode 1 vs 2 per step", d, "step 1 vs plain", relmax(outs[1][0], first_plain),
+          "step 2 vs plain", relmax(outs[1][1], second_plain))
+    assert relmax(outs[1][0], first_plain) <= 1e-14
+    assert relmax(outs[1][1], second_plain) >= 1e-9
+    assert d[0] <= 1e-14 and d[1] <= 1e-14
+    assert d[2] >= 1e-9
+
+
 def test_hysteresis_delays_the_contact_line_but_not_the_angle():
-    """A cap started at 90 degrees on a 60 degree wall.  With the blend (beta
-    = 0.95, a memory of ~1/(1 - beta) = 20 steps) the wall values follow the
-    gradient with a lag, so after 40 steps the contact line has moved less
-    than without it (measured: 0.90 of the distance), but not frozen; the
-    equilibrium angle is the same (the blend's fixed point is the unblended
-    value).  Swapping the factors (a 0.05-step memory) or never updating the
-    history fails one of the bounds."""
+    """A cap started at 90 degrees on a 60 degree wall.  With the recursive
+    blend (reading 1, beta = 0.95, a memory of ~1/(1 - beta) = 20 steps) the
+    wall values follow the gradient with a lag, so after 40 steps the contact
+    line has moved less than without it (measured: 0.90 of the distance),
+    but not frozen; the equilibrium angle is the same (the blend's fixed
+    point is the unblended value).  Swapping the factors (a 0.05-step memory)
+    or never updating the history fails one of the bounds.  Reading 2 blends
+    with the previous step's value only, a one-step memory: it moves almost
+    as far as the plain model (measured 0.99) and farther than reading 1."""
     out = {}
-    for hyst in (False, True):
+    for hyst in (0, 1, 2):
         wl = I.wall_cap_2d(60.0)
         wl.phys = dataclasses.replace(wl.phys, hysteresis=hyst, hyst_beta=0.95)
         o = ref.Oracle(wl)
         x0 = _cap_contact_line(o.fields()[0][:, 0, :])[0]
         o.step(40)
         x1 = _cap_contact_line(o.fields()[0][:, 0, :])[0]
+        if hyst == 2:
+            out[hyst] = (abs(x1 - x0), None)
+            continue
         o.step(7960)
         phi = o.fields()[0][:, 0, :]
         pts = measure.contour_points_xz(phi, z_min=1)
         pts = pts[pts[:, 1] > 2.5]
         xc, zc, Rf = measure.fit_circle(pts)
         out[hyst] = (abs(x1 - x0), theory.cap_angle_from_circle(zc, Rf, 0.5))
-    moved_plain, angle_plain = out[False]
-    moved_hyst, angle_hyst = out[True]
+    moved_plain, angle_plain = out[0]
+    moved_hyst, angle_hyst = out[1]
     assert moved_plain > 0.1
     assert 0.5 * moved_plain <= moved_hyst <= 0.95 * moved_plain
     assert abs(angle_hyst - angle_plain) <= 0.2
+    moved_prev = out[2][0]
+    assert moved_hyst < moved_prev
+    assert 0.97 * moved_plain <= moved_prev <= moved_plain
 
 
 # -------------------------------------------------------------------- P10
