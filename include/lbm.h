@@ -91,11 +91,14 @@ typedef struct lbm_params {
     double u_max;           /* stability limit on |u| (<= 0: NaN check only) */
     int32_t fp16_log2_scale_h; /* FP16 storage scale 2^k of h deviations (0: default) */
     int32_t fp16_log2_scale_g; /* FP16 storage scale 2^k of g deviations (0: default) */
-    int32_t hysteresis;     /* 1: contact-angle hysteresis of the optimised model (Sec. III.A):
-                               each wall link uses hyst_beta * (its value of the previous
-                               step) + (1 - hyst_beta) * (the value from the current
-                               gradient) and keeps the result; the history starts from the
-                               current values at creation and after a restore */
+    int32_t hysteresis;     /* contact-angle hysteresis of the optimised model (Sec. III.A):
+                               each wall link uses hyst_beta * (a value kept from the
+                               previous step) + (1 - hyst_beta) * (the value from the
+                               current gradient).  0: off.  1: the kept value is the blended
+                               value the previous step used (recursive blend).  2: it is the
+                               previous step's unblended, gradient-derived value.  The history
+                               starts from the current values at creation and after a
+                               restore.  Other values: LBM_E_INVAL */
     double hyst_beta;       /* blend factor in [0, 1) (the paper's 0.95) */
     int32_t q_phase;        /* phase-field lattice: 7 (D3Q7, T = 1/4, the default; 0 means 7)
                                or 19 (D3Q19 with the hydrodynamic weights, T = 1/3, the

@@ -571,10 +571,12 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
             a = a < -T(1) + ph[PI_CLAMP_A] ? -T(1) + ph[PI_CLAMP_A] : a;
             const T k2W = ph[PI_K2W];
             // contact-angle hysteresis (Sec. III.A): the wall value of link i
-            // is blended with the one this node used at the previous step
-            // (history slot wslot[n], [18][n_wall] layout); initialisation and
-            // a reset pass record the current values
-            const bool hyst = uni(D->hysteresis) != 0;
+            // is blended with one kept from the previous step (history slot
+            // wslot[n], [18][n_wall] layout): the blended value that step used
+            // (mode 1) or its unblended value (mode 2); initialisation and a
+            // reset pass record the current values
+            const int hmode = uni(D->hysteresis);
+            const bool hyst = hmode != 0;
             T* __restrict__ hist = nullptr;
             int64_t hslot = 0, hstride = 0;
             if (hyst) {
@@ -597,8 +599,9 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
                     if (record) {
                         *hp = ps;
                     } else {
-                        ps = ph[PI_HBETA] * *hp + ph[PI_HBETA1] * ps;
-                        if (MODE == MODE_STEP) *hp = ps;
+                        const T fresh = ps;
+                        ps = ph[PI_HBETA] * *hp + ph[PI_HBETA1] * fresh;
+                        if (MODE == MODE_STEP) *hp = hmode == 2 ? fresh : ps;
                     }
                 }
                 return ps;

@@ -67,6 +67,10 @@ int validate_params(const lbm_params* p, const lbm_geometry* geo) {
         set_error("q_phase %d: the phase lattice is D3Q7 (7) or D3Q19 (19)", p->q_phase);
         return LBM_E_INVAL;
     }
+    if (p->hysteresis < 0 || p->hysteresis > 2) {
+        set_error("hysteresis %d: 0 (off), 1 or 2", p->hysteresis);
+        return LBM_E_INVAL;
+    }
     if (p->hysteresis && !(p->hyst_beta >= 0.0 && p->hyst_beta < 1.0)) {
         set_error("hyst_beta %g outside [0, 1)", p->hyst_beta);
         return LBM_E_INVAL;
@@ -306,7 +310,7 @@ void fill_desc(const lbm_params* p, const lbm_geometry* geo, const LatticeLayout
     d->partials = (double*)(base + L.off_partials);
     d->gbuf = base + L.off_gbuf;
     d->q_phase = phase_q(p);
-    d->hysteresis = p->hysteresis ? 1 : 0;
+    d->hysteresis = p->hysteresis;
     d->hyst_reset = 0;
     d->n_wall = p->hysteresis ? L.n_wall : 0;
     d->wslot = p->hysteresis ? (const int32_t*)(base + L.off_wslot) : nullptr;

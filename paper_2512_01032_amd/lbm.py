@@ -187,7 +187,7 @@ def params_from_workload(wl, storage=None, diag_every=0, u_max=0.0):
         p.face_ramp[f] = 0.0 if fc is None else fc[1]
     p.diag_every = int(diag_every)
     p.u_max = float(u_max)
-    p.hysteresis = 1 if getattr(ph, "hysteresis", False) else 0
+    p.hysteresis = int(getattr(ph, "hysteresis", 0))
     p.hyst_beta = float(getattr(ph, "hyst_beta", 0.0))
     p.q_phase = int(getattr(ph, "q_phase", 7))
     return p

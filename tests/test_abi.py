@@ -47,8 +47,10 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(lbm_params), sizeof(lbm_geometry),
          sizeof(lbm_init), sizeof(lbm_device_ctx), sizeof(lbm_diag), sizeof(lbm_info),
          sizeof(lbm_server_cfg), sizeof(lbm_request), sizeof(lbm_result));
-  printf("%zu %zu %zu\n", offsetof(lbm_params, face_bc), offsetof(lbm_params, diag_every),
-         offsetof(lbm_params, fp16_log2_scale_g));
+  printf("%zu %zu %zu %zu %zu %zu\n", offsetof(lbm_params, face_bc),
+         offsetof(lbm_params, diag_every), offsetof(lbm_params, fp16_log2_scale_g),
+         offsetof(lbm_params, hysteresis), offsetof(lbm_params, hyst_beta),
+         offsetof(lbm_params, q_phase));
   return 0;
 }
 '''
@@ -65,11 +67,13 @@ int main(void) {
     assert sizes == mine
     offs = [int(v) for v in out[1].split()]
     assert offs == [lbm.lbm_params.face_bc.offset, lbm.lbm_params.diag_every.offset,
-                    lbm.lbm_params.fp16_log2_scale_g.offset]
+                    lbm.lbm_params.fp16_log2_scale_g.offset, lbm.lbm_params.hysteresis.offset,
+                    lbm.lbm_params.hyst_beta.offset, lbm.lbm_params.q_phase.offset]
 
 
 @pytest.mark.parametrize("field,value", [("nu_l", 0.0), ("W", -1.0), ("rho_g", 0.0), ("nx", 0),
-                                         ("storage", 9)])
+                                         ("storage", 9), ("q_phase", 8), ("hysteresis", 3),
+                                         ("hysteresis", -1)])
 def test_invalid_parameters_rejected_on_host(field, value):
     from paper_2512_01032_amd import inputs, lbm
     wl = inputs.random_small(8, 6, 5, seed=0)
@@ -123,3 +127,7 @@ def test_footprint_counts_populations():
     assert f64 >= n * (26 * 8 + 8 + 1 + 4)
     assert f16 >= n * (7 * 4 + 19 * 2 + 4 + 1 + 4)
     assert f16 < f32 < f64
+    # the D3Q19 phase lattice stores 12 more h arrays
+    import dataclasses
+    wl.phys = dataclasses.replace(wl.phys, q_phase=19)
+    assert lbm.footprint(wl, "fp32_shift") - f32 >= n * 12 * 4

@@ -332,32 +332,36 @@ def test_full_size_duct_reduced_precision(duct_oracle, storage, bound):
 
 
 # ------------------------------------------------- contact-angle hysteresis
-def _hyst_workload(seed=8):
+def _hyst_workload(seed=8, mode=1):
     import dataclasses
     from paper_2512_01032_amd import inputs
     wl = inputs.random_small(40, 12, 10, seed=seed, walls=True, open_x=True,
                              optimised_model=True, u_amp=0.002)
-    wl.phys = dataclasses.replace(wl.phys, hysteresis=True, hyst_beta=0.95)
+    wl.phys = dataclasses.replace(wl.phys, hysteresis=mode, hyst_beta=0.95)
+    wl.name += "_hyst%d" % mode
     return wl
 
 
-def test_hysteresis_fp64():
-    """Wall values blended with their history (Sec. III.A), walls and
-    pressure faces, FP64: 1e-10 after 30 steps."""
-    g, o = _run_pair(_hyst_workload(), 30)
+@pytest.mark.parametrize("mode", [1, 2])
+def test_hysteresis_fp64(mode):
+    """Wall values blended with their history (Sec. III.A), both readings
+    (1: the blended value of the previous step, 2: its unblended value),
+    walls and pressure faces, FP64: 1e-10 after 30 steps."""
+    g, o = _run_pair(_hyst_workload(mode=mode), 30)
     err = compare_state(g, o, o.kinds())
     print(err, flush=True)
     for k in STRICT:
         assert err[k] <= FP64_TOL, (k, err[k])
 
 
-def test_hysteresis_restore_fp64():
+@pytest.mark.parametrize("mode", [1, 2])
+def test_hysteresis_restore_fp64(mode):
     """Restoring populations restarts the wall-value history from the
     restored state on both sides: GPU and oracle, both restored at step 13,
     agree to 1e-10 after 12 more steps."""
     from oracle import ref
     lbm = _lbm()
-    wl = _hyst_workload(seed=9)
+    wl = _hyst_workload(seed=9, mode=mode)
     a = lbm.Lattice(wl, storage="fp64")
     a.step(13)
     h, gp = a.pops()
@@ -372,8 +376,9 @@ def test_hysteresis_restore_fp64():
         assert err[k] <= FP64_TOL, (k, err[k])
 
 
-def test_hysteresis_fp32_shift():
-    g, o = _run_pair(_hyst_workload(), 50, "fp32_shift")
+@pytest.mark.parametrize("mode", [1, 2])
+def test_hysteresis_fp32_shift(mode):
+    g, o = _run_pair(_hyst_workload(mode=mode), 50, "fp32_shift")
     err = compare_state(g, o, o.kinds())
     print(err, flush=True)
     assert err["phi"] <= 1e-5, err
@@ -447,7 +452,7 @@ def test_d3q19_phase_restore_with_hysteresis_fp64():
     the same way, not with the uninterrupted run)."""
     from oracle import ref
     lbm = _lbm()
-    wl = _q19(_hyst_workload(seed=4))
+    wl = _q19(_hyst_workload(seed=4, mode=2))
     a = lbm.Lattice(wl, storage="fp64")
     a.step(9)
     h, gp = a.pops()
