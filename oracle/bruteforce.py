@@ -69,6 +69,26 @@ class BruteForce:
                 v[a] -= WG[i] * C[i][a] * sm
         nv = np.sqrt((v ** 2).sum(0))
         self.nw = np.where(nv > 0, v / np.where(nv > 0, nv, 1.0), 0.0) * self.fluid
+        # sub-voxel walls: link fractions q[i] (where x + c_i is solid) and
+        # normals from the signed distance, for fluid nodes with a solid link
+        self.q = None
+        sdf = getattr(wl, "sdf", None)
+        if sdf is not None:
+            near = np.zeros(shape, bool)
+            self.q = np.full((19,) + shape, 0.5)
+            for i in range(1, 19):
+                link = shifted(self.solid, C[i], +1) & self.fluid
+                near |= link
+                far = shifted(sdf, C[i], +1)
+                assert (sdf[link] > 0).all() and (far[link] <= 0).all(), "sdf does not straddle"
+                self.q[i] = np.where(link, sdf / np.where(link, sdf - far, 1.0), 0.5)
+            gsd = np.zeros((3,) + shape)
+            for i in range(1, 19):
+                for a in range(3):
+                    gsd[a] += WG[i] * C[i][a] * (shifted(sdf, C[i], +1) - shifted(sdf, C[i], -1))
+            gl = np.sqrt((gsd ** 2).sum(0))
+            ok = near & (gl > 0)
+            self.nw = np.where(ok, gsd / np.where(ok, gl, 1.0), self.nw)
         self.t = 0
         # initial state
         phi = np.where(self.fluid, wl.phi0, 0.0)
@@ -291,7 +311,17 @@ class BruteForce:
             src_solid = shifted(self.solid, C[i], -1)
             io = OPP[i]
             cu = C[io][0] * uw[0] + C[io][1] * uw[1] + C[io][2] * uw[2]
-            bb = gs[io] - 2 * WG[io] * rho * cu / TG
+            corr = 2 * WG[io] * rho * cu / TG
+            if self.q is None:
+                bb = gs[io] - corr
+            else:
+                # interpolated bounce-back with the wall at fraction q of the
+                # link io; below 1/2 the upstream population is this step's
+                # incoming g_io
+                q = self.q[io]
+                hi = gs[io] / (2 * q) + (1 - 1 / (2 * q)) * gs[i] - corr / (2 * q)
+                lo = 2 * q * gs[io] + (1 - 2 * q) * self.g[io] - corr
+                bb = np.where(q >= 0.5, hi, lo)
             gn[i] = np.where(src_solid, bb, shifted(gs[i], C[i], -1))
             if i < QP:
                 hn[i] = np.where(src_solid, hs[io], shifted(hs[i], C[i], -1))

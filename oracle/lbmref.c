@@ -18,8 +18,10 @@
  *   S9  pressure-face ghosts: equilibrium populations from the owner's phi and
  *       u of this step and the face pressure of the next (Dirichlet P, Neumann
  *       u and phi; Sec. III.A)
- *   S8  streaming (pull) with half-way bounce-back at solid links; a ghost
- *       source hands over the populations S9 just set (Sec. III.A friction)
+ *   S8  streaming (pull) with half-way bounce-back at solid links, or with
+ *       sub-voxel walls the linearly interpolated bounce-back of g (h keeps
+ *       the half-way rule); a ghost source hands over the populations S9 just
+ *       set (Sec. III.A friction)
  *   S10 swap lattices, t <- t+1
  * Equation numbers count every numbered display of the paper in order
  * (Eq. 1 the phase-field LB equation ... Eq. 19 the wall value phi_s,i).
@@ -68,6 +70,9 @@ struct lbmref_state {
     long *owner;     /* interior node one step inward from a ghost */
     double *nw;      /* [N*3] unit wall normal into the fluid, 0 without solid links */
     double *hyst;    /* [N*19] wall value each link used last (hysteresis), or NULL */
+    double *qw;      /* [N*19] sub-voxel walls: fraction of link i from node n to the
+                      * wall (0 < q <= 1), set at solid links only; NULL: voxel walls */
+    double *gpre;    /* [N*19] incoming g of the current step (sub-voxel walls only) */
     double *h[2];    /* [N*Q] phase population i of node n at n*Q+i (Q = 7 or 19) */
     double *g[2];    /* [N*19] */
     int cur;
@@ -363,7 +368,7 @@ static int classify(lbmref_state *s, const uint8_t *solid) {
         if (s->kind[o] != K_FLUID) return -1;
         s->owner[n] = o;
     }
-    /* wall normal: -sum of w_i c_i over solid links, normalised */
+    /* wall normal: -sum of w_i c_i over solid links, normalised (voxel walls) */
     for (long n = 0; n < s->N; ++n) {
         double v[3] = {0.0, 0.0, 0.0};
         if (s->kind[n] == K_FLUID) {
@@ -443,7 +448,40 @@ static void macroscopic(lbmref_state *s) {
 }
 
 /* ------------------------------------------------------------------- API */
-lbmref_state *lbmref_create(const lbmref_params *p, const uint8_t *solid,
+/* Sub-voxel walls from a signed distance to the wall surface (positive in
+ * the fluid, the solid nodes at <= 0).  The link from fluid node x to solid
+ * node x + c_i crosses the surface at the fraction
+ *     q = sdf(x) / (sdf(x) - sdf(x + c_i))
+ * of its length (linear interpolation of the distance along the link), and
+ * the wall normal into the fluid is the normalised gradient of sdf by the
+ * central differences of Eq. 16.  Invalid (-1): a fluid node with a solid
+ * link whose distances do not straddle the surface. */
+static int walls_from_sdf(lbmref_state *s, const double *sdf) {
+    for (long n = 0; n < s->N; ++n) {
+        if (s->kind[n] != K_FLUID) continue;
+        int any = 0;
+        for (int i = 1; i < 19; ++i) {
+            long m = neighbour(s, n, i, +1);
+            if (s->kind[m] != K_SOLID) continue;
+            any = 1;
+            double a = sdf[n], b = sdf[m];
+            if (!(a > 0.0) || !(b <= 0.0)) return -1;
+            s->qw[19 * n + i] = a / (a - b);
+        }
+        if (!any) continue;
+        double gs[3] = {0.0, 0.0, 0.0};
+        for (int i = 1; i < 19; ++i) {
+            double d = sdf[neighbour(s, n, i, +1)] - sdf[neighbour(s, n, i, -1)];
+            for (int a = 0; a < 3; ++a) gs[a] += d * CV[i][a] * WG[i];
+        }
+        double gn = sqrt(gs[0] * gs[0] + gs[1] * gs[1] + gs[2] * gs[2]);
+        if (gn > 0.0)
+            for (int a = 0; a < 3; ++a) s->nw[3 * n + a] = gs[a] / gn;
+    }
+    return 0;
+}
+
+lbmref_state *lbmref_create(const lbmref_params *p, const uint8_t *solid, const double *sdf,
                             const double *phi0, const double *u0, const double *P0) {
     if (!p || !phi0 || p->nx < 1 || p->ny < 1 || p->nz < 1) return NULL;
     if (p->W <= 0.0 || p->M <= 0.0 || p->rho_l <= 0.0 || p->rho_g <= 0.0) return NULL;
@@ -459,6 +497,8 @@ lbmref_state *lbmref_create(const lbmref_params *p, const uint8_t *solid,
     s->owner = malloc(N * sizeof(long));
     s->nw = malloc(3 * N * sizeof(double));
     s->hyst = p->hysteresis ? calloc(19 * N, sizeof(double)) : NULL;
+    s->qw = sdf ? calloc(19 * N, sizeof(double)) : NULL;
+    s->gpre = sdf ? calloc(19 * N, sizeof(double)) : NULL;
     for (int k = 0; k < 2; ++k) {
         s->h[k] = calloc((long)phase_Q(p) * N, sizeof(double));
         s->g[k] = calloc(19 * N, sizeof(double));
@@ -468,13 +508,14 @@ lbmref_state *lbmref_create(const lbmref_params *p, const uint8_t *solid,
     s->grad = calloc(3 * N, sizeof(double)); s->lap = calloc(N, sizeof(double));
     s->mu = calloc(N, sizeof(double));
     if (!s->kind || !s->mat || !s->gface || !s->owner || !s->nw || (p->hysteresis && !s->hyst) ||
+        (sdf && (!s->qw || !s->gpre)) ||
         !s->h[0] || !s->h[1] ||
         !s->g[0] || !s->g[1] || !s->phi || !s->rho || !s->u || !s->P || !s->grad ||
         !s->lap || !s->mu) {
         lbmref_destroy(s);
         return NULL;
     }
-    if (classify(s, solid) != 0) {
+    if (classify(s, solid) != 0 || (sdf && walls_from_sdf(s, sdf) != 0)) {
         lbmref_destroy(s);
         return NULL;
     }
@@ -505,6 +546,7 @@ lbmref_state *lbmref_create(const lbmref_params *p, const uint8_t *solid,
 void lbmref_destroy(lbmref_state *s) {
     if (!s) return;
     free(s->kind); free(s->mat); free(s->gface); free(s->owner); free(s->nw); free(s->hyst);
+    free(s->qw); free(s->gpre);
     for (int k = 0; k < 2; ++k) { free(s->h[k]); free(s->g[k]); }
     free(s->phi); free(s->rho); free(s->u); free(s->P); free(s->grad); free(s->lap);
     free(s->mu);
@@ -521,6 +563,7 @@ static void one_step(lbmref_state *s) {
     double *hA = s->h[s->cur], *gA = s->g[s->cur];
     double *hB = s->h[1 - s->cur], *gB = s->g[1 - s->cur];
     phase_moment(s); /* S1 */
+    if (s->gpre) memcpy(s->gpre, gA, 19 * N * sizeof(double));
     /* S2-S7: collide every fluid node in place in lattice A */
 #pragma omp parallel for schedule(static) if (s->N >= 16384)
     for (long n = 0; n < N; ++n) {
@@ -561,8 +604,27 @@ static void one_step(lbmref_state *s) {
             int io = s->opp[i];
             double gv;
             if (s->kind[x] == K_SOLID) {
+                /* the population g*_io(y) sent toward the wall comes back as
+                 * g_i(y); a wall moving with u_w adds -2 w rho c.u_w / T */
                 double cu = CV[io][0] * uw[0] + CV[io][1] * uw[1] + CV[io][2] * uw[2];
-                gv = gA[19 * y + io] - 2.0 * WG[io] * s->rho[y] * cu / TG;
+                double mw = 2.0 * WG[io] * s->rho[y] * cu / TG;
+                if (!s->qw) {
+                    gv = gA[19 * y + io] - mw;
+                } else {
+                    /* linear interpolated bounce-back (Bouzidi, Firdaouss and
+                     * Lallemand 2001) with the wall at fraction q of the link.
+                     * q >= 1/2: between g*_io(y) and g*_i(y); the moving-wall
+                     * term scales by 1/(2q).  q < 1/2: between g*_io(y) and the
+                     * population g*_io(y - c_io) one link upstream, taken as the
+                     * one that arrived at y along io at this step (its value a
+                     * step earlier: exact for a steady flow, and local) */
+                    double q = s->qw[19 * y + io];
+                    if (q >= 0.5)
+                        gv = gA[19 * y + io] / (2.0 * q) + (1.0 - 1.0 / (2.0 * q)) * gA[19 * y + i] -
+                             mw / (2.0 * q);
+                    else
+                        gv = 2.0 * q * gA[19 * y + io] + (1.0 - 2.0 * q) * s->gpre[19 * y + io] - mw;
+                }
                 if (i < Qh) hB[(long)Qh * y + i] = hA[(long)Qh * y + io];
             } else {
                 gv = gA[19 * x + i];

@@ -76,9 +76,14 @@ typedef struct lbmref_diag {
 typedef struct lbmref_state lbmref_state;
 
 /* solid[n]: 0 = fluid, 1+k = solid of material k (k < 16).  May be NULL.
+ * sdf[N]: NULL for voxel walls (half-way bounce-back, normals from the solid
+ * links); else sub-voxel walls given by the signed distance to the wall
+ * surface (> 0 at fluid nodes next to a wall, <= 0 at their solid
+ * neighbours): per-link wall fractions for the interpolated bounce-back of g
+ * and wall normals from the distance gradient.
  * phi0[N] required; u0[3][N] and P0[N] may be NULL (0 and P_ref).
  * Returns NULL on invalid input or allocation failure. */
-lbmref_state *lbmref_create(const lbmref_params *p, const uint8_t *solid,
+lbmref_state *lbmref_create(const lbmref_params *p, const uint8_t *solid, const double *sdf,
                             const double *phi0, const double *u0, const double *P0);
 void lbmref_destroy(lbmref_state *s);
 void lbmref_step(lbmref_state *s, long nsteps);

@@ -72,7 +72,7 @@ def lib():
         L = ctypes.CDLL(LIB_PATH)
         dp = ctypes.POINTER(ctypes.c_double)
         L.lbmref_create.restype = ctypes.c_void_p
-        L.lbmref_create.argtypes = [ctypes.POINTER(Params), ctypes.c_void_p, dp, dp, dp]
+        L.lbmref_create.argtypes = [ctypes.POINTER(Params), ctypes.c_void_p, dp, dp, dp, dp]
         L.lbmref_destroy.argtypes = [ctypes.c_void_p]
         L.lbmref_step.argtypes = [ctypes.c_void_p, ctypes.c_long]
         L.lbmref_step_count.argtypes = [ctypes.c_void_p]
@@ -144,10 +144,12 @@ class Oracle:
         u0 = None if wl.u0 is None else np.ascontiguousarray(wl.u0, dtype=np.float64)
         P0 = None if wl.P0 is None else np.ascontiguousarray(wl.P0, dtype=np.float64)
         solid = None if wl.solid is None else np.ascontiguousarray(wl.solid, dtype=np.uint8)
-        self._keep = [phi0, u0, P0, solid]
+        sdf = getattr(wl, "sdf", None)
+        sdf = None if sdf is None else np.ascontiguousarray(sdf, dtype=np.float64)
+        self._keep = [phi0, u0, P0, solid, sdf]
         h = L.lbmref_create(ctypes.byref(self.params),
                             None if solid is None else solid.ctypes.data,
-                            _dptr(phi0), _dptr(u0), _dptr(P0))
+                            _dptr(sdf), _dptr(phi0), _dptr(u0), _dptr(P0))
         if not h:
             raise ValueError("oracle rejected the workload %s" % wl.name)
         self.h = ctypes.c_void_p(h)

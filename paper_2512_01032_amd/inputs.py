@@ -81,6 +81,9 @@ class Workload:
     phys: Physics
     phi0: np.ndarray
     solid: Optional[np.ndarray] = None
+    # signed distance to the wall surface (> 0 in the fluid) for sub-voxel
+    # walls; None: voxel walls half-way between fluid and solid nodes
+    sdf: Optional[np.ndarray] = None
     u0: Optional[np.ndarray] = None
     P0: Optional[np.ndarray] = None
     faces: tuple = (None,) * 6
@@ -295,10 +298,13 @@ def serving_trace(n=256, rate=50.0, seed=1, edges=(32, 48, 64, 96, 128),
 
 # ------------------------------------------------------------- small test cases
 def random_small(nx, ny, nz, seed, walls=False, open_x=False, storage="fp64",
-                 u_amp=0.01, optimised_model=False):
+                 u_amp=0.01, optimised_model=False, subvoxel=False):
     """A small lattice with a random smooth phi field, small random velocity
     and optional walls (y = 0 and z = 0 solid layers of two materials) and
-    pressure faces along x; used for parity on tiny grids."""
+    pressure faces along x; used for parity on tiny grids.  subvoxel (with
+    walls): the wall surfaces are wavy sheets inside the cells between the
+    solid layers and the first fluid nodes, given by a signed distance, so
+    every wall link has its own fraction and the normals tilt."""
     rng = np.random.default_rng(seed)
     ph = Physics(W=4.0, nu_g=0.1)
     if optimised_model:
@@ -324,9 +330,39 @@ def random_small(nx, ny, nz, seed, walls=False, open_x=False, storage="fp64",
         # a small obstacle gives concave and convex corners
         solid[nz // 2, ny // 2, nx // 2] = 1
         th[0], th[1] = float(rng.uniform(30, 80)), float(rng.uniform(100, 150))
+    sdf = None
+    if walls and subvoxel:
+        # level sets y = 0.7 + 0.25 sin(kx) (+ a z wave) and z = 0.6 + 0.3 cos(kx):
+        # the y = 0, z = 0 layers stay solid, the first fluid layers fluid
+        k = 2 * np.pi / nx
+        sy = y - (0.7 + 0.25 * np.sin(k * x) + 0.05 * np.cos(2 * np.pi * z / nz))
+        sz = z - (0.6 + 0.3 * np.cos(k * x))
+        sdf = np.minimum(sy, sz)
+        # the obstacle: a sphere of radius 0.8 around its node
+        c = (nx // 2, ny // 2, nz // 2)
+        so = np.sqrt((x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2) - 0.8
+        sdf = np.minimum(sdf, so)
+        assert ((sdf <= 0) == (solid > 0)).all()
     if open_x:
         faces[0] = (ph.P_ref + 2e-4, 1e-6)
         faces[1] = (ph.P_ref, 0.0)
     return Workload("random_%dx%dx%d_s%d" % (nx, ny, nz, seed), nx, ny, nz, ph, phi,
-                    solid=solid, u0=u0, P0=P0, faces=tuple(faces), theta_deg=tuple(th),
+                    solid=solid, sdf=sdf, u0=u0, P0=P0, faces=tuple(faces), theta_deg=tuple(th),
                     storage=storage)
+
+
+def offset_plates(ny, delta, nx=1, nz=1, ph=None, phi0=None, theta=90.0, storage="fp64"):
+    """Plates normal to y with their surfaces offset by delta (0 <= delta < 1)
+    from the lattice-aligned case: walls at y0 = 0.5 + delta and
+    y1 = ny - 1.5 - delta, given by the signed distance min(y - y0, y1 - y);
+    nodes at or beyond a surface are solid.  Single phase (phi = 1) unless
+    phi0 is given."""
+    ph = ph if ph is not None else Physics()
+    x, y, z = _grid(nx, ny, nz)
+    y0, y1 = 0.5 + delta, ny - 1.5 - delta
+    sdf = np.minimum(y - y0, y1 - y)
+    solid = (sdf <= 0).astype(np.uint8)
+    phi = np.ones((nz, ny, nx)) if phi0 is None else phi0
+    return Workload("plates_%d_d%.2f" % (ny, delta), nx, ny, nz, ph, phi, solid=solid, sdf=sdf,
+                    theta_deg=(theta,) * 16, storage=storage,
+                    meta={"y0": y0, "y1": y1})

@@ -31,7 +31,11 @@ def relmax(a, b):
                                        (dict(walls=True, open_x=True, optimised_model=True), 1, 7),
                                        (dict(walls=True, open_x=True, optimised_model=True), 2, 7),
                                        (dict(walls=True, open_x=True, optimised_model=True), False, 19),
-                                       (dict(walls=True, open_x=True, optimised_model=True), 2, 19)])
+                                       (dict(walls=True, open_x=True, optimised_model=True), 2, 19),
+                                       (dict(walls=True, open_x=True, optimised_model=True,
+                                             subvoxel=True), False, 7),
+                                       (dict(walls=True, open_x=True, optimised_model=True,
+                                             subvoxel=True), 1, 19)])
 def test_bruteforce_reference_agrees(kw, hyst, q):
     """Whole-lattice NumPy transcription (np.roll streaming, masks) vs the
     node-by-node C oracle on a tiny lattice: pins indexing, periodic wrap,
@@ -519,3 +523,72 @@ def test_mobility_correction_sets_the_rounding_sensitivity():
     print(out)
     assert out[False] <= 1e-6
     assert out[True] >= 100 * out[False]
+
+
+# --------------------------------------------------------- sub-voxel walls
+def test_subvoxel_walls_at_half_way_are_voxel_walls():
+    """A signed distance that puts the wall surfaces exactly half-way between
+    the fluid and solid nodes (plates, delta = 0) gives q = 1/2 on every link
+    and the axis normal: bitwise the voxel-wall model, with a two-phase field
+    touching both walls (wetting at 50 and 120 degrees, optimised model)."""
+    ny = 16
+    x, y, z = I._grid(24, ny, 5)
+    phi0 = I.tanh_profile(np.sqrt((x - 11.5) ** 2 + (y - 2.0) ** 2) - 6.0, 4.0)
+    ph = I.optimised(I.Physics(W=4.0, nu_g=0.1))
+    a = I.offset_plates(ny, 0.0, nx=24, nz=5, ph=ph, phi0=phi0, theta=50.0)
+    a.theta_deg = (50.0, 120.0) + (90.0,) * 14
+    a.solid = a.solid * np.where(y < ny / 2, 1, 2).astype(np.uint8)
+    b = dataclasses.replace(a, sdf=None)
+    oa, ob = ref.Oracle(a), ref.Oracle(b)
+    oa.step(30)
+    ob.step(30)
+    ha, ga = oa.pops()
+    hb, gb = ob.pops()
+    assert np.array_equal(ha, hb) and np.array_equal(ga, gb)
+
+
+@pytest.mark.parametrize("delta", [0.15, 0.35, 0.6, 0.85])
+def test_subvoxel_poiseuille_between_offset_plates(delta):
+    """Plates offset by delta from the lattice-aligned case (walls at
+    y0 = 0.5 + delta and y1 = ny - 1.5 - delta): with the interpolated
+    bounce-back the steady profile is the parabola
+    F/(2 rho nu) (y - y0)(y1 - y) within 1% (measured 0.3-0.7%); the same
+    solid nodes with half-way walls miss it by 4-11%, since their walls sit
+    at the wrong place."""
+    ny = 18
+    ph = I.Physics(nu_l=0.1, nu_g=0.1, rho_g=1.0, F_ex=(1e-5, 0.0, 0.0))
+    errs = {}
+    for sub in (True, False):
+        wl = I.offset_plates(ny, delta, ph=ph)
+        if not sub:
+            wl.sdf = None
+        o = ref.Oracle(wl)
+        o.step(4000)
+        u = o.fields()[2][0, 0, :, 0]
+        fl = wl.solid[0, :, 0] == 0
+        yy = np.arange(ny)[fl]
+        ut = theory.poiseuille_profile(yy, wl.meta["y0"], wl.meta["y1"], 1e-5, 1.0, 0.1)
+        errs[sub] = np.abs(u[fl] - ut).max() / ut.max()
+    print(delta, errs)
+    assert errs[True] <= 0.01
+    assert errs[False] >= 0.03
+
+
+def test_subvoxel_walls_conserve_phi_mass():
+    """h keeps the half-way bounce-back at sub-voxel walls, so phi mass is
+    exact on a closed domain (no pressure faces) with wavy walls."""
+    wl = I.random_small(12, 10, 9, seed=5, walls=True, optimised_model=True, subvoxel=True,
+                        u_amp=0.002)
+    o = ref.Oracle(wl)
+    m0 = o.diagnostics()["phi_sum"]
+    o.step(200)
+    m1 = o.diagnostics()["phi_sum"]
+    assert abs(m1 - m0) <= 1e-12 * abs(m0)
+
+
+def test_subvoxel_rejects_a_distance_that_does_not_straddle_the_wall():
+    wl = I.offset_plates(12, 0.3)
+    wl.sdf = wl.sdf.copy()
+    wl.sdf[0, 0, 0] = 0.2          # a solid node with a positive distance
+    with pytest.raises(ValueError):
+        ref.Oracle(wl)
