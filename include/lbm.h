@@ -103,16 +103,29 @@ typedef struct lbm_params {
     int32_t q_phase;        /* phase-field lattice: 7 (D3Q7, T = 1/4, the default; 0 means 7)
                                or 19 (D3Q19 with the hydrodynamic weights, T = 1/3, the
                                lattice Sec. II names for Eq. 2); any other value: LBM_E_INVAL */
+    int32_t subvoxel;       /* 0: voxel walls, half-way between fluid and solid nodes.
+                               1: sub-voxel walls (walls off the lattice, Sec. IV.A offsets
+                               and inclined or curved walls) given by lbm_geometry.sdf: g
+                               takes the linear interpolated bounce-back at each link's wall
+                               fraction and the wall normal is the distance gradient; h keeps
+                               the half-way rule (exact phi mass).  Other values: LBM_E_INVAL */
 } lbm_params;
 
-/* Voxel geometry.  solid[n] = 0: fluid; 1 + k: solid of material k (< 16).
+/* Geometry.  solid[n] = 0: fluid; 1 + k: solid of material k (< 16).
  * Non-solid nodes on a pressure-face layer become pressure ghosts; a ghost may
  * lie on one pressure face only and its inward neighbour must be fluid.
  * solid may be NULL (no walls). theta_deg[k] in (0, 180): contact angle of
- * material k, measured through the phi = 1 phase (Sec. II.B). */
+ * material k, measured through the phi = 1 phase (Sec. II.B).
+ * sdf[N] (only with lbm_params.subvoxel = 1, else NULL): signed distance to
+ * the wall surface, > 0 at every fluid node with a solid neighbour and <= 0
+ * at those solid neighbours; the link from fluid x to solid x + c_i crosses
+ * the wall at q = sdf(x) / (sdf(x) - sdf(x + c_i)) of its length.  A pair that
+ * does not straddle the surface: LBM_E_INVAL.  Host memory, read during
+ * lbm_create / lbm_submit only. */
 typedef struct lbm_geometry {
     const uint8_t *solid;
     double theta_deg[16];
+    const double *sdf;
 } lbm_geometry;
 
 enum lbm_init_kind { LBM_INIT_FIELDS = 0, LBM_INIT_POPULATIONS = 1 };

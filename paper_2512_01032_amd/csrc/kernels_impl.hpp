@@ -406,7 +406,9 @@ __device__ inline void h_eq_pair(int i, const NodeState<T>& s, T href, T& hp, T&
 #ifndef SWEEP_WAVES_PER_EU
 #define SWEEP_WAVES_PER_EU 1
 #endif
-template <typename T, typename SH, typename SG, int MODE, bool DIAG, int TX, int PAR, int QP>
+// SV: instance with the interpolated bounce-back of sub-voxel walls (step
+// mode only; lattices without sub-voxel walls keep half-way walls in it).
+template <typename T, typename SH, typename SG, int MODE, bool DIAG, int TX, int PAR, int QP, bool SV = false>
 __global__ void __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(SWEEP_WAVES_PER_EU)))
 sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut ro, InitIn in) {
     // LDS ring of phi and flags: each plane holds the tile plus a one-node
@@ -542,20 +544,36 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
 #pragma unroll
         for (int i = 1; i < 19; i += 2) pair_sum(i, nbv(i), nbv(i + 1));
         T nw[3] = {T(0), T(0), T(0)};
+        // sub-voxel walls: per-slot table of link fractions and wall normal
+        const bool svx = uni(D->subvoxel) != 0;
+        const T* __restrict__ wtab = nullptr;
+        int64_t wsl = 0, wstr = 0;
+        if (solid && svx) {
+            wtab = unip((const T*)D->wall);
+            wstr = uni(D->n_wall);
+            wsl = D->wslot[n];
+        }
         if (solid) {
             // wetting (Eqs. 17-19).  Wall normal into the fluid from the solid
-            // links; neutral pre-gradient (the node's own phi at the solid
-            // links); w = -cos(theta) n + sin(theta) t with t the unit
-            // tangential part of the pre-gradient; phi_s,i from the tanh
-            // profile through phi(x) shifted by d_i = w . c_i; the stencil is
-            // evaluated again with phi_s,i at the solid links
-            for (int i = 1; i < 19; ++i) {
-                if (!((solid >> i) & 1u)) continue;
-                nw[0] -= T(wg(i) * CX[i]); nw[1] -= T(wg(i) * CY[i]); nw[2] -= T(wg(i) * CZ[i]);
+            // links (sub-voxel walls: from the table); neutral pre-gradient
+            // (the node's own phi at the solid links); w = -cos(theta) n +
+            // sin(theta) t with t the unit tangential part of the pre-gradient;
+            // phi_s,i from the tanh profile through phi(x) shifted by
+            // d_i = w . c_i; the stencil is evaluated again with phi_s,i at the
+            // solid links
+            if (svx) {
+                nw[0] = wtab[(QG - 1) * wstr + wsl];
+                nw[1] = wtab[QG * wstr + wsl];
+                nw[2] = wtab[(QG + 1) * wstr + wsl];
+            } else {
+                for (int i = 1; i < 19; ++i) {
+                    if (!((solid >> i) & 1u)) continue;
+                    nw[0] -= T(wg(i) * CX[i]); nw[1] -= T(wg(i) * CY[i]); nw[2] -= T(wg(i) * CZ[i]);
+                }
+                const T nn = dev_sqrt(nw[0] * nw[0] + nw[1] * nw[1] + nw[2] * nw[2]);
+                const T inn = nn > T(0) ? T(1) / nn : T(0);
+                nw[0] *= inn; nw[1] *= inn; nw[2] *= inn;
             }
-            const T nn = dev_sqrt(nw[0] * nw[0] + nw[1] * nw[1] + nw[2] * nw[2]);
-            const T inn = nn > T(0) ? T(1) / nn : T(0);
-            nw[0] *= inn; nw[1] *= inn; nw[2] *= inn;
             gx = gy = gz = lap = T(0);
 #pragma unroll
             for (int i = 1; i < 19; i += 2)
@@ -731,8 +749,41 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
             const T tau = (T(1) - Fm) * ph[PI_TAU_G] + Fm * ph[PI_TAU_L];
             st.om = (T(1) - T(1) / tau) * i2Tg2;
         }
-        // D3Q19 write-back (AA slots of parity PAR)
         const T sg = ph[PI_SG];
+        // ---- sub-voxel walls (MODE_STEP): linear interpolated bounce-back of
+        //      g (after the write-back, below) needs f_i^in, the population
+        //      that entered the node along c_i this step, for every solid link
+        //      i; the write-back overwrites its slot, so it is parked first
+        //      where nothing else reads or writes during this step: an odd
+        //      step in the node's own slot (x, ibar), the final destination,
+        //      which the odd write-back does not touch; an even step in the
+        //      solid neighbour's slot (x + c_i, i).
+        if (SV && MODE == MODE_STEP && svx && solid) {
+            if (PAR == 1) {
+                // f_i^in sits in (x - c_i, ibar), or in (x, i) where x - c_i is
+                // solid, and is parked in (x, ibar).  With both ends of a pair
+                // solid (a one-node gap) each link's source is the other's
+                // destination, so a pair is loaded before it is stored.
+                for (int i = 1; i < QG; i += 2) {
+                    const int j = i + 1;                          // OPP[i]
+                    const bool si = (solid >> i) & 1u, sj = (solid >> j) & 1u;
+                    if (!si && !sj) continue;
+                    SG fi_in = SG(0), fj_in = SG(0);
+                    if (si) fi_in = (SG)(sj ? Store<SG>::ld(gb, i, (uint32_t)n)
+                                            : Store<SG>::ld(gb, j, nb.at(-CX[i], -CY[i], -CZ[i])));
+                    if (sj) fj_in = (SG)(si ? Store<SG>::ld(gb, j, (uint32_t)n)
+                                            : Store<SG>::ld(gb, i, nb.at(-CX[j], -CY[j], -CZ[j])));
+                    if (si) Store<SG>::st(gb, j, (uint32_t)n, fi_in);
+                    if (sj) Store<SG>::st(gb, i, (uint32_t)n, fj_in);
+                }
+            } else {
+                // f_i^in sits in the own slot (x, i); parked in (x + c_i, i)
+                for (int i = 1; i < QG; ++i)
+                    if ((solid >> i) & 1u)
+                        Store<SG>::st(gb, i, nb.at(CX[i], CY[i], CZ[i]), Store<SG>::ld(gb, i, (uint32_t)n));
+            }
+        }
+        // D3Q19 write-back (AA slots of parity PAR)
         auto put_g = [&](int i, T v) {
             const T vs = Store<SG>::scaled ? v * sg : v;
             if (MODE == MODE_STEP) {
@@ -810,11 +861,29 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
                     uw[2] = st.u[2] - nw[2] * un;
                     slip = true;
                 }
-                if (PAR == 1 || slip) {
+                if ((SV && svx) || PAR == 1 || slip) {
                     for (int i = 1; i < QG; ++i) {
                         if (!((solid >> i) & 1u)) continue;
                         const T cuw = T(CX[i]) * uw[0] + T(CY[i]) * uw[1] + T(CZ[i]) * uw[2];
-                        const T v = g_out<T, MODE>(i, st, rdif) - T(6 * wg(i)) * st.rho * cuw;
+                        const T m = T(6 * wg(i)) * st.rho * cuw;     // moving-wall term
+                        const T fi = g_out<T, MODE>(i, st, rdif);
+                        T v = fi - m;
+                        if (SV && svx) {
+                            // linear interpolated bounce-back at the wall
+                            // fraction q of link i (f_i^in parked above):
+                            //   q >= 1/2: f*_i / (2q) + (1 - 1/(2q)) f*_ibar - m / (2q)
+                            //   q <  1/2: 2q f*_i + (1 - 2q) f_i^in - m
+                            const T q = wtab[(int64_t)(i - 1) * wstr + wsl];
+                            if (q >= T(0.5)) {
+                                const T r = T(1) / (T(2) * q);
+                                v = v * r + (T(1) - r) * g_out<T, MODE>(OPP[i], st, rdif);
+                            } else {
+                                T fin = (T)(PAR == 1 ? Store<SG>::ld(gb, OPP[i], (uint32_t)n)
+                                                     : Store<SG>::ld(gb, i, nb.at(CX[i], CY[i], CZ[i])));
+                                if (Store<SG>::scaled) fin *= ph[PI_INV_SG];
+                                v = T(2) * q * fi + (T(1) - T(2) * q) * fin - m;
+                            }
+                        }
                         Store<SG>::st(gb, OPP[i], (uint32_t)n, Store<SG>::scaled ? v * sg : v);
                     }
                 }
@@ -1040,6 +1109,10 @@ hipError_t launch_sweep_tp(int mode, Desc* d, const Tile* tiles, int ntiles, int
         case MODE_STEP:
             if (diag) sweep_kernel<T, SH, SG, MODE_STEP, true, TX, PAR, QP><<<grid, block, 0, s>>>(d, tiles, ro, in);
             else sweep_kernel<T, SH, SG, MODE_STEP, false, TX, PAR, QP><<<grid, block, 0, s>>>(d, tiles, ro, in);
+            break;
+        case MODE_STEP_SV:
+            if (diag) sweep_kernel<T, SH, SG, MODE_STEP, true, TX, PAR, QP, true><<<grid, block, 0, s>>>(d, tiles, ro, in);
+            else sweep_kernel<T, SH, SG, MODE_STEP, false, TX, PAR, QP, true><<<grid, block, 0, s>>>(d, tiles, ro, in);
             break;
         case MODE_READ:
             sweep_kernel<T, SH, SG, MODE_READ, true, TX, PAR, QP><<<grid, block, 0, s>>>(d, tiles, ro, in);

@@ -30,6 +30,7 @@ namespace pflbm {
 static const int HCX[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
 static const int HCY[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
 static const int HCZ[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+static double host_wg(int i) { return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0); }
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
@@ -65,6 +66,14 @@ int validate_params(const lbm_params* p, const lbm_geometry* geo) {
     }
     if (p->q_phase != 0 && p->q_phase != 7 && p->q_phase != 19) {
         set_error("q_phase %d: the phase lattice is D3Q7 (7) or D3Q19 (19)", p->q_phase);
+        return LBM_E_INVAL;
+    }
+    if (p->subvoxel != 0 && p->subvoxel != 1) {
+        set_error("subvoxel %d: 0 (voxel walls) or 1 (walls from a signed distance)", p->subvoxel);
+        return LBM_E_INVAL;
+    }
+    if (geo && (p->subvoxel != 0) != (geo->sdf != nullptr)) {
+        set_error(p->subvoxel ? "subvoxel = 1 needs geometry.sdf" : "geometry.sdf is given but subvoxel = 0");
         return LBM_E_INVAL;
     }
     if (p->hysteresis < 0 || p->hysteresis > 2) {
@@ -160,9 +169,13 @@ static void layout_offsets(const lbm_params* p, int64_t ntiles, int64_t nghosts,
     L->off_partials = o; o = align256(o + (size_t)ntiles * NPART * sizeof(double));
     L->off_gbuf = o; o = align256(o + (size_t)3 * L->gface_count * sphi);
     L->off_ghosts = o; o = align256(o + (size_t)nghosts * sizeof(GhostRef));
-    // hysteresis: per-node history slot, 18 wall values per near-wall node
-    L->off_wslot = o; if (p->hysteresis) o = align256(o + (size_t)N * 4);
+    // per-node slot of near-wall fluid nodes (hysteresis, sub-voxel walls);
+    // hysteresis: 18 wall values per slot; sub-voxel walls: 18 link
+    // fractions and the wall normal per slot
+    const bool slots = p->hysteresis || p->subvoxel;
+    L->off_wslot = o; if (slots) o = align256(o + (size_t)N * 4);
     L->off_hyst = o; if (p->hysteresis) o = align256(o + (size_t)(QG - 1) * L->n_wall * sphi);
+    L->off_wall = o; if (p->subvoxel) o = align256(o + (size_t)WALL_ROWS * L->n_wall * sphi);
     L->total = o;
 }
 
@@ -254,15 +267,62 @@ int build_layout(const lbm_params* p, const lbm_geometry* geo, int lat, LatticeL
             }
         }
     }
-    // history slots of the wall values, in node order (coalesced along x)
+    // slots of the near-wall fluid nodes, in node order (coalesced along x)
     L->n_wall = 0;
-    if (p->hysteresis) {
+    std::vector<double>().swap(L->wall);
+    if (p->hysteresis || p->subvoxel) {
         L->wslot.assign(N, -1);
         for (int64_t n = 0; n < N; ++n)
             if ((L->link[n] & SOLID_MASK) && flag_kind(L->flag[n]) == KIND_FLUID)
                 L->wslot[n] = (int32_t)L->n_wall++;
     } else {
         std::vector<int32_t>().swap(L->wslot);
+    }
+    if (p->subvoxel) {
+        // sub-voxel walls from the signed distance (> 0 in the fluid): the
+        // link from fluid node x to solid node x + c_i crosses the surface at
+        // q = sdf(x) / (sdf(x) - sdf(x + c_i)); the wall normal is the
+        // normalised central-difference gradient of sdf (D3Q19 weights), or
+        // the solid-link rule where that gradient vanishes
+        const double* sdf = geo->sdf;
+        const int64_t nw = L->n_wall;
+        L->wall.assign((size_t)WALL_ROWS * nw, 0.0);
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x) {
+                    const int64_t n = x + (int64_t)nx * (y + (int64_t)ny * z);
+                    const int32_t sl = L->wslot[n];
+                    if (sl < 0) continue;
+                    const uint32_t m = L->link[n] & SOLID_MASK;
+                    double gsd[3] = {0.0, 0.0, 0.0}, vox[3] = {0.0, 0.0, 0.0};
+                    for (int i = 1; i < 19; ++i) {
+                        const int64_t np = idx(x + HCX[i], y + HCY[i], z + HCZ[i]);
+                        const int64_t nm = idx(x - HCX[i], y - HCY[i], z - HCZ[i]);
+                        const double d = sdf[np] - sdf[nm];
+                        gsd[0] += host_wg(i) * HCX[i] * d;
+                        gsd[1] += host_wg(i) * HCY[i] * d;
+                        gsd[2] += host_wg(i) * HCZ[i] * d;
+                        if (!((m >> i) & 1u)) continue;
+                        vox[0] -= host_wg(i) * HCX[i];
+                        vox[1] -= host_wg(i) * HCY[i];
+                        vox[2] -= host_wg(i) * HCZ[i];
+                        const double a = sdf[n], b = sdf[np];
+                        if (!(a > 0.0) || !(b <= 0.0)) {
+                            set_error("sdf at (%d,%d,%d) = %g and its solid neighbour along link %d = %g "
+                                      "do not straddle the wall surface", x, y, z, a, i, b);
+                            return LBM_E_INVAL;
+                        }
+                        L->wall[(size_t)(i - 1) * nw + sl] = a / (a - b);
+                    }
+                    double gn = sqrt(gsd[0] * gsd[0] + gsd[1] * gsd[1] + gsd[2] * gsd[2]);
+                    const double* v = gsd;
+                    if (!(gn > 0.0)) {
+                        v = vox;
+                        gn = sqrt(vox[0] * vox[0] + vox[1] * vox[1] + vox[2] * vox[2]);
+                    }
+                    for (int a = 0; a < 3; ++a)
+                        L->wall[(size_t)(QG - 1 + a) * nw + sl] = gn > 0.0 ? v[a] / gn : 0.0;
+                }
     }
     // tile table: keep tiles holding at least one non-solid node
     const int tx = choose_tx(nx), ty = NTHREADS / tx, tz = choose_tz(p, tx);
@@ -312,9 +372,12 @@ void fill_desc(const lbm_params* p, const lbm_geometry* geo, const LatticeLayout
     d->q_phase = phase_q(p);
     d->hysteresis = p->hysteresis;
     d->hyst_reset = 0;
-    d->n_wall = p->hysteresis ? L.n_wall : 0;
-    d->wslot = p->hysteresis ? (const int32_t*)(base + L.off_wslot) : nullptr;
+    const bool slots = p->hysteresis || p->subvoxel;
+    d->n_wall = slots ? L.n_wall : 0;
+    d->wslot = slots ? (const int32_t*)(base + L.off_wslot) : nullptr;
     d->hyst = p->hysteresis ? (void*)(base + L.off_hyst) : nullptr;
+    d->subvoxel = p->subvoxel ? 1 : 0;
+    d->wall = p->subvoxel ? (void*)(base + L.off_wall) : nullptr;
     for (int f = 0; f < 6; ++f) d->gface_base[f] = L.gface_base[f];
     d->gface_count = L.gface_count;
     d->counter = (unsigned int*)(base + L.off_counter);
@@ -414,8 +477,22 @@ int upload_and_init(const lbm_params* p, const lbm_geometry* geo, const lbm_init
     HIPCHK(hipMemsetAsync(base + L.off_partials, 0, L.tiles.size() * NPART * sizeof(double), s));
     HIPCHK(hipMemcpyAsync(base + L.off_flag, L.flag.data(), N, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(base + L.off_link, L.link.data(), (size_t)N * 4, hipMemcpyHostToDevice, s));
-    if (p->hysteresis)
+    if (p->hysteresis || p->subvoxel)
         HIPCHK(hipMemcpyAsync(base + L.off_wslot, L.wslot.data(), (size_t)N * 4, hipMemcpyHostToDevice, s));
+    if (p->subvoxel && L.n_wall) {
+        // wall table in the compute type (a synchronous copy: the host
+        // buffer is temporary)
+        const size_t cnt = (size_t)WALL_ROWS * L.n_wall;
+        if (sphi == 8) {
+            HIPCHK(hipMemcpyAsync(base + L.off_wall, L.wall.data(), cnt * 8, hipMemcpyHostToDevice, s));
+            HIPCHK(hipStreamSynchronize(s));
+        } else {
+            std::vector<float> wf(cnt);
+            for (size_t k = 0; k < cnt; ++k) wf[k] = (float)L.wall[k];
+            HIPCHK(hipMemcpyAsync(base + L.off_wall, wf.data(), cnt * 4, hipMemcpyHostToDevice, s));
+            HIPCHK(hipStreamSynchronize(s));
+        }
+    }
     HIPCHK(hipMemcpyAsync(base + L.off_tiles, L.tiles.data(), L.tiles.size() * sizeof(Tile),
                           hipMemcpyHostToDevice, s));
     if (!L.ghosts.empty())

@@ -19,15 +19,16 @@ struct LatticeLayout {
     int tx = 64, ty = 4, tz = 16;
     int64_t N = 0;
     int64_t n_fluid = 0, n_ghost = 0, n_solid = 0;
-    int64_t n_wall = 0;           // near-wall fluid nodes with a history slot (hysteresis)
+    int64_t n_wall = 0;           // near-wall fluid nodes with a slot (hysteresis, sub-voxel walls)
     size_t off_desc = 0, off_counter = 0, off_h = 0, off_g = 0, off_phi = 0, off_flag = 0,
            off_link = 0, off_tiles = 0, off_partials = 0, off_gbuf = 0, off_ghosts = 0,
-           off_wslot = 0, off_hyst = 0, total = 0;
+           off_wslot = 0, off_hyst = 0, off_wall = 0, total = 0;
     int64_t gface_base[6] = {0, 0, 0, 0, 0, 0};
     int64_t gface_count = 0;      // face-buffer entries (per velocity component)
     std::vector<uint8_t> flag;
     std::vector<uint32_t> link;
-    std::vector<int32_t> wslot;   // hysteresis: history slot of each node (-1: none)
+    std::vector<int32_t> wslot;   // slot of each near-wall fluid node (-1: none)
+    std::vector<double> wall;     // sub-voxel walls: [WALL_ROWS][n_wall] link fractions, normal
     std::vector<Tile> tiles;
     std::vector<GhostRef> ghosts;
 };

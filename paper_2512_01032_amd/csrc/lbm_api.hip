@@ -171,7 +171,7 @@ extern "C" int lbm_step(lbm_handle* h, int64_t nsteps) {
         const int par = (int)(t & 1);
         HIPRET(launch_phi(storage, qp, par, h->ddesc, h->dtiles, h->ntiles, h->stream));
         if (h->timing) HIPRET(hipEventRecord(e1, h->stream));
-        HIPRET(launch_sweep(storage, qp, MODE_STEP, h->L.tx, par, h->ddesc, h->dtiles, h->ntiles, diag, ro, in,
+        HIPRET(launch_sweep(storage, qp, h->p.subvoxel ? MODE_STEP_SV : MODE_STEP, h->L.tx, par, h->ddesc, h->dtiles, h->ntiles, diag, ro, in,
                             h->stream));
         if (h->nghosts)
             HIPRET(launch_ghosts(storage, qp, h->ddesc, h->dghosts, h->nghosts, h->stream));

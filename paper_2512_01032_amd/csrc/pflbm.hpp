@@ -41,6 +41,7 @@ constexpr int LINK_OWNER_SHIFT = 24;
 constexpr int ST_FP64 = 0, ST_FP32 = 1, ST_FP32_SHIFT = 2, ST_FP16_G = 3, ST_FP16_ALL = 4;
 
 constexpr uint32_t SOLID_MASK = 0x7FFFEu;  // link bits 1..18
+constexpr int WALL_ROWS = 21;              // sub-voxel wall table: 18 fractions + normal
 
 struct alignas(16) Tile {
     int32_t lat;      // lattice index in the descriptor array
@@ -72,10 +73,15 @@ struct alignas(256) Desc {
     int64_t gface_base[6];         // first entry of each face plane in gbuf
     int64_t gface_count;           // entries per velocity component
     void* hyst;                    // [18][n_wall] wall values of the last step (compute type)
-    const int32_t* wslot;          // [N] slot of a near-wall fluid node in hyst
+    const int32_t* wslot;          // [N] slot of a near-wall fluid node in hyst and wall
     int64_t n_wall;                // near-wall fluid nodes (hysteresis only, else 0)
-    int32_t hysteresis;            // 1: wall values blended with their history
+    int32_t hysteresis;            // 1, 2: wall values blended with their history (two readings)
     int32_t hyst_reset;            // a read pass records the current wall values instead
+    void* wall;                    // sub-voxel walls: [WALL_ROWS][n_wall] (compute type):
+                                   // rows 0-17 the wall fraction q of links 1-18, rows
+                                   // 18-20 the unit wall normal into the fluid
+    int32_t subvoxel;              // 1: interpolated bounce-back of g at the wall fractions
+    int32_t pad_sv;
     // time
     int64_t step;                  // advanced on the device after each step's ghost pass
     int64_t t0;                    // step counter value at physical time 0
@@ -122,6 +128,7 @@ enum { P_PHI = 0, P_MX, P_MY, P_MZ, P_UMAX, P_NAN, P_PLIQ, P_NLIQ, P_PGAS, P_NGA
 constexpr int MODE_STEP = 0;   // stream + collide, AA in place
 constexpr int MODE_READ = 1;   // macroscopic fields / populations to output buffers
 constexpr int MODE_INIT = 2;   // equilibria from (phi, u, P) into even-parity slots
+constexpr int MODE_STEP_SV = 3;  // launcher mode: MODE_STEP with sub-voxel walls enabled
 
 struct GhostRef {              // one pressure ghost: lattice and node
     int32_t lat;

@@ -83,6 +83,7 @@ struct Job {
     lbm_params p;
     lbm_geometry geo;
     std::vector<uint8_t> solid;
+    std::vector<double> sdf;
     std::vector<double> phi0, u0, P0;
     int64_t nsteps = 0;
     double arrival_s = 0.0;
@@ -119,7 +120,7 @@ struct lbm_server {
     size_t tiles_cap = 0;
     GhostRef* dghosts = nullptr;
     size_t ghosts_cap = 0;
-    struct Group { int qp, tx, off, n; };
+    struct Group { int qp, tx, off, n, sv = 0; };   // sv: lattices with sub-voxel walls
     std::vector<Group> groups;         // sweep launches: one per (phase lattice, tile width)
     std::vector<Group> phi_groups;     // phi launches: one per phase lattice (tx unused)
     std::vector<Group> ghost_groups;   // ghost launches: one per phase lattice (tx unused)
@@ -229,9 +230,12 @@ int admit_one(lbm_server* s) {
     std::vector<double>().swap(job->u0);
     std::vector<double>().swap(job->P0);
     std::vector<uint8_t>().swap(job->solid);
+    std::vector<double>().swap(job->sdf);
+    std::vector<double>().swap(job->L.wall);
     std::vector<uint8_t>().swap(job->L.flag);
     std::vector<uint32_t>().swap(job->L.link);
     job->geo.solid = nullptr;
+    job->geo.sdf = nullptr;
     job->t_admit = s->now();
     job->step = 0;
     s->resident_nodes += job->L.N;
@@ -241,8 +245,8 @@ int admit_one(lbm_server* s) {
 }
 
 // Concatenated tile tables of all resident lattices, grouped by phase
-// lattice and, within it, by tile width (each kernel instance handles one
-// of each); ghost tables grouped by phase lattice.
+// lattice and, within it, by tile width and wall kind (each kernel instance
+// handles one of each); ghost tables grouped by phase lattice.
 int rebuild_tables(lbm_server* s) {
     std::vector<Tile> tiles;
     std::vector<GhostRef> ghosts;
@@ -253,12 +257,17 @@ int rebuild_tables(lbm_server* s) {
     for (int qp : {7, 19}) {
         const int qoff = (int)tiles.size();
         for (int tx : {64, 32, 16}) {
-            const int off = (int)tiles.size();
-            for (auto& j : s->active) {
-                if (j->L.tx != tx || phase_q(&j->p) != qp) continue;
-                for (Tile t : j->L.tiles) { t.lat = j->slot; tiles.push_back(t); }
+            // lattices with sub-voxel walls run their own instance of the
+            // sweep, the others the plain one: each lattice always runs the
+            // same code as when alone (bitwise the same result)
+            for (int sv : {0, 1}) {
+                const int off = (int)tiles.size();
+                for (auto& j : s->active) {
+                    if (j->L.tx != tx || phase_q(&j->p) != qp || (j->p.subvoxel ? 1 : 0) != sv) continue;
+                    for (Tile t : j->L.tiles) { t.lat = j->slot; tiles.push_back(t); }
+                }
+                if ((int)tiles.size() > off) s->groups.push_back({qp, tx, off, (int)tiles.size() - off, sv});
             }
-            if ((int)tiles.size() > off) s->groups.push_back({qp, tx, off, (int)tiles.size() - off});
         }
         if ((int)tiles.size() > qoff) s->phi_groups.push_back({qp, 0, qoff, (int)tiles.size() - qoff});
         const int goff = (int)ghosts.size();
@@ -309,7 +318,7 @@ hipError_t enqueue_steps(lbm_server* s) {
                 e = launch_phi(storage, g.qp, par, s->dtable, s->dtiles + g.off, g.n, s->stream, 0);
         for (const auto& g : s->groups)
             if (e == hipSuccess)
-                e = launch_sweep(storage, g.qp, MODE_STEP, g.tx, par, s->dtable, s->dtiles + g.off, g.n,
+                e = launch_sweep(storage, g.qp, g.sv ? MODE_STEP_SV : MODE_STEP, g.tx, par, s->dtable, s->dtiles + g.off, g.n,
                                  0, ro, in, s->stream);
         for (const auto& g : s->ghost_groups)
             if (e == hipSuccess)
@@ -537,6 +546,7 @@ extern "C" int lbm_submit(lbm_server* s, const lbm_request* req, uint64_t* ticke
     const int64_t N = (int64_t)job->p.nx * job->p.ny * job->p.nz;
     try {
         if (req->geometry.solid) job->solid.assign(req->geometry.solid, req->geometry.solid + N);
+        if (req->geometry.sdf) job->sdf.assign(req->geometry.sdf, req->geometry.sdf + N);
         job->phi0.assign(req->init.phi, req->init.phi + N);
         if (req->init.u) job->u0.assign(req->init.u, req->init.u + 3 * N);
         if (req->init.P) job->P0.assign(req->init.P, req->init.P + N);
@@ -545,6 +555,7 @@ extern "C" int lbm_submit(lbm_server* s, const lbm_request* req, uint64_t* ticke
         return LBM_E_NOMEM;
     }
     job->geo.solid = job->solid.empty() ? nullptr : job->solid.data();
+    job->geo.sdf = job->sdf.empty() ? nullptr : job->sdf.data();
     job->nsteps = req->nsteps;
     job->arrival_s = req->arrival_s;
     job->t_submit = t;

@@ -43,11 +43,12 @@ class lbm_params(ctypes.Structure):
         ("diag_every", c_int32), ("u_max", c_double),
         ("fp16_log2_scale_h", c_int32), ("fp16_log2_scale_g", c_int32),
         ("hysteresis", c_int32), ("hyst_beta", c_double), ("q_phase", c_int32),
+        ("subvoxel", c_int32),
     ]
 
 
 class lbm_geometry(ctypes.Structure):
-    _fields_ = [("solid", ctypes.c_void_p), ("theta_deg", c_double * 16)]
+    _fields_ = [("solid", ctypes.c_void_p), ("theta_deg", c_double * 16), ("sdf", ctypes.c_void_p)]
 
 
 class lbm_init(ctypes.Structure):
@@ -190,6 +191,7 @@ def params_from_workload(wl, storage=None, diag_every=0, u_max=0.0):
     p.hysteresis = int(getattr(ph, "hysteresis", 0))
     p.hyst_beta = float(getattr(ph, "hyst_beta", 0.0))
     p.q_phase = int(getattr(ph, "q_phase", 7))
+    p.subvoxel = 0 if getattr(wl, "sdf", None) is None else 1
     return p
 
 
@@ -211,6 +213,8 @@ class Lattice:
         geo = lbm_geometry()
         self._solid = _arr(wl.solid, np.uint8)
         geo.solid = None if self._solid is None else self._solid.ctypes.data
+        self._sdf = _arr(getattr(wl, "sdf", None))
+        geo.sdf = None if self._sdf is None else self._sdf.ctypes.data
         for k in range(16):
             geo.theta_deg[k] = wl.theta_deg[k]
         init = lbm_init()
@@ -328,6 +332,8 @@ class Server:
         solid = _arr(wl.solid, np.uint8)
         phi0, u0, P0 = _arr(wl.phi0), _arr(wl.u0), _arr(wl.P0)
         req.geometry.solid = None if solid is None else solid.ctypes.data
+        sdf = _arr(getattr(wl, "sdf", None))
+        req.geometry.sdf = None if sdf is None else sdf.ctypes.data
         for k in range(16):
             req.geometry.theta_deg[k] = wl.theta_deg[k]
         req.init.kind = LBM_INIT_FIELDS

@@ -6,6 +6,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -73,7 +74,7 @@ int main(void) {
 
 @pytest.mark.parametrize("field,value", [("nu_l", 0.0), ("W", -1.0), ("rho_g", 0.0), ("nx", 0),
                                          ("storage", 9), ("q_phase", 8), ("hysteresis", 3),
-                                         ("hysteresis", -1)])
+                                         ("hysteresis", -1), ("subvoxel", 2)])
 def test_invalid_parameters_rejected_on_host(field, value):
     from paper_2512_01032_amd import inputs, lbm
     wl = inputs.random_small(8, 6, 5, seed=0)
@@ -114,6 +115,40 @@ def test_invalid_geometry_rejected_on_host():
     with pytest.raises(lbm.LbmError) as ei:
         lbm.Lattice(wl)
     assert ei.value.code == lbm.LBM_E_INVAL
+
+
+def test_subvoxel_geometry_rejected_on_host():
+    """subvoxel = 1 needs a signed distance, a distance needs subvoxel = 1,
+    and a distance that does not straddle a wall link is rejected."""
+    from paper_2512_01032_amd import inputs, lbm
+    wl = inputs.offset_plates(12, 0.3, nx=8, nz=4)
+    sdf = wl.sdf
+    wl.sdf = None
+    p = lbm.params_from_workload(wl)
+    p.subvoxel = 1
+    g = lbm.lbm_geometry()
+    for k in range(16):
+        g.theta_deg[k] = 90.0
+    solid = np.ascontiguousarray(wl.solid, np.uint8)
+    g.solid = solid.ctypes.data
+    init = lbm.lbm_init()
+    phi = np.ascontiguousarray(wl.phi0)
+    init.phi = phi.ctypes.data
+    h = ctypes.c_void_p()
+    for bad_sdf, sv in ((None, 1), (sdf, 0)):
+        p.subvoxel = sv
+        keep = None if bad_sdf is None else np.ascontiguousarray(bad_sdf)
+        g.sdf = None if keep is None else keep.ctypes.data
+        with pytest.raises(lbm.LbmError) as ei:
+            lbm.check(lbm.lbm_create(ctypes.byref(p), ctypes.byref(g), ctypes.byref(init), None,
+                                     ctypes.byref(h)))
+        assert ei.value.code == lbm.LBM_E_INVAL
+    wl.sdf = sdf.copy()
+    wl.sdf[0, 1, 0] = -0.1      # a fluid node next to the wall with a negative distance
+    with pytest.raises(lbm.LbmError) as ei:
+        lbm.Lattice(wl)
+    assert ei.value.code == lbm.LBM_E_INVAL
+    assert b"straddle" in lbm.lbm_last_error()
 
 
 def test_footprint_counts_populations():

@@ -494,3 +494,76 @@ def test_d3q19_phase_reduced_precision(storage, mc, bound):
     if storage == "fp32_shift" and not mc:
         for k in ("h", "g", "P"):
             assert err[k] <= 1e-5, (k, err)
+
+
+# ----------------------------------------------------------- sub-voxel walls
+@pytest.mark.parametrize("shape,kw,steps,q", [
+    ((8, 6, 7), dict(open_x=True, optimised_model=True), 9, 7),
+    ((70, 13, 9), dict(open_x=True), 11, 7),                      # TX = 16, ragged
+    ((33, 40, 5), dict(optimised_model=True), 8, 7),              # ragged in y
+    ((250, 5, 4), dict(open_x=True, optimised_model=True), 6, 7),  # TX = 64, four tiles
+    ((40, 12, 10), dict(open_x=True, optimised_model=True), 12, 19),
+])
+def test_subvoxel_walls_small_lattices_fp64(shape, kw, steps, q):
+    """Wavy wall surfaces and a sphere inside the solid layers' cells: every
+    wall link has its own fraction (both branches of the interpolated
+    bounce-back), tilted normals; odd and even steps; FP64 1e-10."""
+    import dataclasses
+    from paper_2512_01032_amd import inputs
+    wl = inputs.random_small(*shape, seed=21, walls=True, subvoxel=True, u_amp=0.002, **kw)
+    wl.phys = dataclasses.replace(wl.phys, q_phase=q)
+    g, o = _run_pair(wl, steps)
+    err = compare_state(g, o, o.kinds())
+    print(err, flush=True)
+    for k in STRICT:
+        assert err[k] <= FP64_TOL, (k, err[k])
+
+
+def test_subvoxel_offset_plates_poiseuille_fp64():
+    """Single-phase flow between plates offset by 0.3 (wall fractions 0.2 and
+    0.8 on the two sides): 300 steps, FP64 1e-10 against the oracle."""
+    from paper_2512_01032_amd import inputs
+    ph = inputs.Physics(nu_l=0.1, nu_g=0.1, rho_g=1.0, F_ex=(1e-5, 0.0, 0.0))
+    wl = inputs.offset_plates(18, 0.3, nx=20, nz=3, ph=ph)
+    g, o = _run_pair(wl, 300)
+    err = compare_state(g, o, o.kinds())
+    print(err, flush=True)
+    for k in ("phi", "P", "h", "g", "mom"):
+        assert err[k] <= FP64_TOL, (k, err[k])
+
+
+def test_subvoxel_restore_fp64():
+    """Odd-step restore with sub-voxel walls = uninterrupted run, bitwise."""
+    from paper_2512_01032_amd import inputs
+    lbm = _lbm()
+    wl = inputs.random_small(24, 10, 12, seed=3, walls=True, open_x=True, subvoxel=True,
+                             optimised_model=True, u_amp=0.002)
+    a = lbm.Lattice(wl, storage="fp64")
+    a.step(20)
+    c = lbm.Lattice(wl, storage="fp64")
+    c.step(11)
+    hc, gc = c.pops()
+    d = lbm.Lattice(wl, storage="fp64", pops=np.concatenate([hc, gc]), step=11)
+    d.step(9)
+    for pa, pd in zip(a.pops(), d.pops()):
+        assert np.array_equal(pa, pd)
+
+
+@pytest.mark.parametrize("storage", ["fp32_shift", "fp16_shift_g"])
+def test_subvoxel_reduced_precision(storage):
+    """FP32 arithmetic at sub-voxel walls, mobility correction off (R24 is
+    about the correction, not the walls): phi, h within 1e-5 (FP32) and
+    phi 1e-3 (FP16 g) after 40 steps."""
+    import dataclasses
+    from paper_2512_01032_amd import inputs
+    wl = inputs.random_small(40, 12, 10, seed=6, walls=True, open_x=True, subvoxel=True,
+                             optimised_model=True, u_amp=0.002)
+    wl.phys = dataclasses.replace(wl.phys, mobility_corr=False)
+    g, o = _run_pair(wl, 40, storage)
+    err = compare_state(g, o, o.kinds())
+    print(storage, err, flush=True)
+    if storage == "fp32_shift":
+        for k in ("phi", "h", "g", "P"):
+            assert err[k] <= 1e-5, (k, err)
+    else:
+        assert err["phi"] <= 1e-3, err

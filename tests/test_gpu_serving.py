@@ -144,3 +144,22 @@ def test_alone_equals_mix_bitwise_two_phase_lattices():
         wls[k].name += "_q19"
     res = _serve(lbm, wls, hbm_budget=1 << 30, use_graph=True, ticks_per_sync=6)
     _check_same(lbm, wls, res)
+
+
+def test_alone_equals_mix_bitwise_with_subvoxel_walls():
+    """A batch mixing lattices with sub-voxel walls and voxel walls of one
+    tile width: each kind runs its own instance of the sweep, as when alone,
+    so every result is bitwise the request run alone."""
+    from paper_2512_01032_amd import inputs
+    lbm = _lbm()
+    wls = [
+        inputs.random_small(40, 12, 10, seed=8, walls=True, open_x=True, optimised_model=True,
+                            u_amp=0.002, storage="fp32_shift", subvoxel=True),   # tile width 16
+        inputs.random_small(40, 12, 10, seed=9, walls=True, open_x=True, optimised_model=True,
+                            u_amp=0.002, storage="fp32_shift"),                  # tile width 16
+        inputs.droplet_on_wall(32, 50.0, 21),
+    ]
+    for wl in wls[:2]:
+        wl.steps = 17
+    res = _serve(lbm, wls, hbm_budget=1 << 30, use_graph=True, ticks_per_sync=6)
+    _check_same(lbm, wls, res)
