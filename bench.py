@@ -309,6 +309,50 @@ def run_gpu(wl, storage, steps, warmup, torch):
     return lat, info, el, phi_ms / max(n, 1), sweep_ms / max(n, 1)
 
 
+def variants_leg(wl, args, torch):
+    """The method's options on the benchmark duct (FP32 shifted storage):
+    contact-angle hysteresis (Sec. III.A), the D3Q19 phase lattice, and
+    sub-voxel walls (every wall surface 0.3 cells into the fluid).  Each
+    reports fluid MLUPS and the sweep against the HBM roofline with its own
+    population bytes per node (the hysteresis history and the wall table
+    are reported as extra bytes per near-wall node)."""
+    import dataclasses
+    from paper_2512_01032_amd import inputs
+    out = {}
+    names = [v for v in args.variants.split(",") if v]
+    for name in names:
+        v = dataclasses.replace(wl)
+        qh, extra = 7, 0
+        if name == "hysteresis":
+            v.phys = dataclasses.replace(wl.phys, hysteresis=1, hyst_beta=0.95)
+            extra = 2 * 18 * 4
+        elif name == "d3q19_phase":
+            v.phys = dataclasses.replace(wl.phys, q_phase=19)
+            qh = 19
+        elif name == "subvoxel":
+            v.sdf = inputs.duct_sdf(wl, 0.3)
+            extra = 21 * 4
+        else:
+            raise SystemExit("unknown variant %s" % name)
+        print("[bench] variant %s: 5 warmup + %d timed steps" % (name, args.variant_steps),
+              file=sys.stderr, flush=True)
+        lat, info, el, phi_ms, sweep_ms = run_gpu(v, "fp32_shift", args.variant_steps, 5, torch)
+        lat.close()
+        b_alg = 2 * (qh * 4 + 19 * 4)
+        nf = info["n_fluid"]
+        achieved = b_alg * nf / (sweep_ms * 1e-3) / 1e9
+        out[name] = {"mlups_fluid": round(nf * args.variant_steps / el / 1e6, 2),
+                     "ms_per_step": round(el / args.variant_steps * 1e3, 4),
+                     "sweep_ms": round(sweep_ms, 4), "phi_pass_ms": round(phi_ms, 4),
+                     "bytes_per_fluid_update": b_alg,
+                     "extra_bytes_per_near_wall_update": extra,
+                     "sweep_GBs": round(achieved, 1),
+                     "sweep_frac_hbm": round(achieved / HBM_PEAK_GBS, 4)}
+        print("[bench] variant %s: %.1f MLUPS (fluid), sweep %.3f ms, %.0f GB/s alg"
+              % (name, out[name]["mlups_fluid"], sweep_ms, achieved), file=sys.stderr, flush=True)
+    return out
+
+
 def storage_bytes(storage):
     return {"fp64": (8, 8), "fp32": (4, 4), "fp32_shift": (4, 4),
             "fp16_shift_g": (4, 2), "fp16_shift_all": (2, 2)}[storage]
@@ -332,6 +376,10 @@ def main():
                          "(0 nodes: no cap)")
     ap.add_argument("--no-serve-baseline", action="store_true",
                     help="skip the one-at-a-time replay of the serving trace")
+    ap.add_argument("--variants", default="hysteresis,d3q19_phase,subvoxel",
+                    help="options of the method timed on the same duct in FP32 shifted storage "
+                         "(comma list; empty: skip)")
+    ap.add_argument("--variant-steps", type=int, default=60)
     ap.add_argument("--fold-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="fold two rocprofv3 --pmc counter_collection.csv files (FETCH_SIZE, "
                          "WRITE_SIZE) into the per-launch traffic record and exit")
@@ -387,6 +435,7 @@ def main():
             del lattices[m]
 
     primary = results["fp32_shift"]
+    variants = variants_leg(wl, args, torch)
     cpu = None
     errors = {}
     accuracy = None
@@ -452,6 +501,7 @@ def main():
         "max_abs_dphi_vs_oracle": errors,
         "accuracy_vs_oracle": accuracy,
         "serving": serving,
+        "variants": variants,
         "kernel_hash": kernel_hash(),
     }
     print(json.dumps(line))

@@ -844,12 +844,14 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
             else place_pops<T, SH, QP, PAR>(hb, (uint32_t)n, nb, solid, ph[PI_SH], B);
         }
 
-        // ---- solid links (Sec. III.A).  Half-way bounce-back returns the
-        //      population to the node's own slot: the odd step wrote it to the
-        //      solid node's slot above (never read), so it is written again;
-        //      the even step already wrote it to the own slot.  Inside the
-        //      free-slip band the wall moves with the tangential fluid velocity
-        //      (moving-wall bounce-back), which changes the returned g.
+        // ---- solid links (Sec. III.A).  Half-way bounce-back returns g*_i to
+        //      the node's own slot (x, ibar): the even write-back already put
+        //      it there, the odd one into the solid node's slot (x + c_i, i),
+        //      never read.  Inside the free-slip band the wall moves with the
+        //      tangential fluid velocity (moving-wall bounce-back), which
+        //      changes the returned g.  The post-collision values are read
+        //      back from where the write-back stored them (slots only this
+        //      node writes during the step) rather than recomputed.
         if (solid) {
             if (MODE == MODE_STEP) {
                 T uw[3] = {T(0), T(0), T(0)};
@@ -861,30 +863,46 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
                     uw[2] = st.u[2] - nw[2] * un;
                     slip = true;
                 }
+                const T isg = ph[PI_INV_SG];
+                auto back = [&](int q, uint32_t node) -> T {
+                    const T v = (T)Store<SG>::ld(gb, q, node);
+                    return Store<SG>::scaled ? v * isg : v;
+                };
                 if ((SV && svx) || PAR == 1 || slip) {
-                    for (int i = 1; i < QG; ++i) {
-                        if (!((solid >> i) & 1u)) continue;
+                    // value returned along ibar for solid link i (reads only)
+                    auto wall_value = [&](int i) -> T {
                         const T cuw = T(CX[i]) * uw[0] + T(CY[i]) * uw[1] + T(CZ[i]) * uw[2];
                         const T m = T(6 * wg(i)) * st.rho * cuw;     // moving-wall term
-                        const T fi = g_out<T, MODE>(i, st, rdif);
-                        T v = fi - m;
-                        if (SV && svx) {
-                            // linear interpolated bounce-back at the wall
-                            // fraction q of link i (f_i^in parked above):
-                            //   q >= 1/2: f*_i / (2q) + (1 - 1/(2q)) f*_ibar - m / (2q)
-                            //   q <  1/2: 2q f*_i + (1 - 2q) f_i^in - m
-                            const T q = wtab[(int64_t)(i - 1) * wstr + wsl];
-                            if (q >= T(0.5)) {
-                                const T r = T(1) / (T(2) * q);
-                                v = v * r + (T(1) - r) * g_out<T, MODE>(OPP[i], st, rdif);
-                            } else {
-                                T fin = (T)(PAR == 1 ? Store<SG>::ld(gb, OPP[i], (uint32_t)n)
-                                                     : Store<SG>::ld(gb, i, nb.at(CX[i], CY[i], CZ[i])));
-                                if (Store<SG>::scaled) fin *= ph[PI_INV_SG];
-                                v = T(2) * q * fi + (T(1) - T(2) * q) * fin - m;
-                            }
+                        // g*_i: even (x, ibar), odd (x + c_i, i)
+                        const T fi = PAR == 0 ? back(OPP[i], (uint32_t)n)
+                                              : back(i, nb.at(CX[i], CY[i], CZ[i]));
+                        if (!(SV && svx)) return fi - m;
+                        // linear interpolated bounce-back at the wall fraction q
+                        // of link i (f_i^in parked above):
+                        //   q >= 1/2: g*_i / (2q) + (1 - 1/(2q)) g*_ibar - m / (2q)
+                        //   q <  1/2: 2q g*_i + (1 - 2q) f_i^in - m
+                        const T q = wtab[(int64_t)(i - 1) * wstr + wsl];
+                        if (q >= T(0.5)) {
+                            // g*_ibar: even (x, i), odd (x - c_i, ibar)
+                            const T fo = PAR == 0 ? back(i, (uint32_t)n)
+                                                  : back(OPP[i], nb.at(-CX[i], -CY[i], -CZ[i]));
+                            const T r = T(1) / (T(2) * q);
+                            return (fi - m) * r + (T(1) - r) * fo;
                         }
-                        Store<SG>::st(gb, OPP[i], (uint32_t)n, Store<SG>::scaled ? v * sg : v);
+                        const T fin = PAR == 1 ? back(OPP[i], (uint32_t)n)
+                                               : back(i, nb.at(CX[i], CY[i], CZ[i]));
+                        return T(2) * q * fi + (T(1) - T(2) * q) * fin - m;
+                    };
+                    // a pair (i, ibar) with both ends solid reads the slots the
+                    // other writes: both values are formed before either store
+                    for (int i = 1; i < QG; i += 2) {
+                        const int j = i + 1;                          // OPP[i]
+                        const bool si = (solid >> i) & 1u, sj = (solid >> j) & 1u;
+                        if (!si && !sj) continue;
+                        const T vi = si ? wall_value(i) : T(0);
+                        const T vj = sj ? wall_value(j) : T(0);
+                        if (si) Store<SG>::st(gb, j, (uint32_t)n, Store<SG>::scaled ? vi * sg : vi);
+                        if (sj) Store<SG>::st(gb, i, (uint32_t)n, Store<SG>::scaled ? vj * sg : vj);
                     }
                 }
             } else if (PAR == 1) {

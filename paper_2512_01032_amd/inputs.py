@@ -220,6 +220,27 @@ def constricted_duct(nx=256, ny=256, nz=512, step_z=256, theta=120.0, ramp_to=2e
                     meta={"slugs": slugs, "step_z": step_z})
 
 
+def duct_sdf(wl, offset=0.3):
+    """Signed distance of the constricted duct's fluid region with every wall
+    surface moved offset (0 <= offset < 0.5) into the fluid from its half-way
+    position: the same solid nodes, every wall link at fraction 0.5 - offset.
+    Built from the planes of the wide duct, the narrow square and the step
+    face (max of the two parts, min within each)."""
+    nx, ny, nz = wl.nx, wl.ny, wl.nz
+    step_z = wl.meta["step_z"]
+    x, y, z = _grid(nx, ny, nz)
+    lo, hi = 0.5 + offset, -1.5 - offset
+    wide = np.minimum(np.minimum(x - lo, nx + hi - x), np.minimum(y - lo, ny + hi - y))
+    qx0, qx1 = nx // 4, nx - nx // 4
+    qy0, qy1 = ny // 4, ny - ny // 4
+    narrow = np.minimum(np.minimum(x - (qx0 - 0.5 + offset), (qx1 - 0.5 - offset) - x),
+                        np.minimum(y - (qy0 - 0.5 + offset), (qy1 - 0.5 - offset) - y))
+    before_step = np.minimum(wide, (step_z - 0.5 - offset) - z)
+    sdf = np.maximum(before_step, np.minimum(narrow, wide))
+    assert ((sdf <= 0) == (wl.solid > 0)).all()
+    return sdf
+
+
 def wall_cap_2d(theta, nx=64, nz=24, R=11.0, W=4.0, steps=8000, storage="fp64"):
     """Quasi-2D cylindrical cap (y of width 1, periodic) on a wall at z = 0
     (material 0, angle theta) under a neutral wall at z = nz - 1, centred at
