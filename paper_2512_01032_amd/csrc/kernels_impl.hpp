@@ -164,10 +164,24 @@ template <typename T> struct Phys {
 };
 
 template <typename T> __device__ inline T clamp01(T v) { return v < T(0) ? T(0) : (v > T(1) ? T(1) : v); }
-__device__ inline double dev_tanh(double v) { return tanh(v); }
-__device__ inline float dev_tanh(float v) { return tanhf(v); }
+// Square root, quotient and exponential of the compute type.  FP64 keeps the
+// correctly rounded forms; FP32 takes the hardware approximations
+// (v_sqrt_f32, v_rcp_f32, v_exp_f32, about one ulp each), far below the
+// rounding of the FP32 and FP16 population storage, at a tenth of the
+// instructions.
 __device__ inline double dev_sqrt(double v) { return sqrt(v); }
-__device__ inline float dev_sqrt(float v) { return sqrtf(v); }
+__device__ inline float dev_sqrt(float v) { return __builtin_amdgcn_sqrtf(v); }
+__device__ inline double dev_div(double a, double b) { return a / b; }
+__device__ inline float dev_div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ inline double dev_exp(double v) { return exp(v); }
+__device__ inline float dev_exp(float v) { return __builtin_amdgcn_exp2f(v * 1.44269504088896341f); }
+// (1 + tanh v) / 2 in its logistic form 1 / (1 + e^(-2v)): one exponential
+// and one quotient; saturates to 0 and 1 through e^(-2v) = inf and 0
+template <typename T> __device__ inline T half_tanh1(T v) { return dev_div(T(1), T(1) + dev_exp(T(-2) * v)); }
+// tanh v = 1 - 2 / (e^(2v) + 1) in FP32 (exactly 0 at v = 0, +-1 at the
+// ends); the library tanh in FP64
+__device__ inline double dev_tanh(double v) { return tanh(v); }
+__device__ inline float dev_tanh(float v) { return 1.0f - 2.0f * __builtin_amdgcn_rcpf(dev_exp(2.0f * v) + 1.0f); }
 
 __device__ inline int wrapc(int v, int n) {
     v %= n;
@@ -419,6 +433,7 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
     __shared__ uint8_t s_flag[4][LN];
     __shared__ double s_red[NPART][NTHREADS / 64];
     __shared__ int s_last;
+    __shared__ T s_cs[2][16];   // cos and sin of each wall material's contact angle
 
     const Tile tl = load_tile(tiles);
     Desc* D = descs + tl.lat;
@@ -477,6 +492,10 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
     // slot of plane z-2 (last read in the previous iteration) after it, so
     // their latency overlaps the population traffic, and one barrier per
     // plane orders the ring.
+    if (tid < 16) {
+        s_cs[0][tid] = (T)D->cos_t[tid];
+        s_cs[1][tid] = (T)D->sin_t[tid];
+    }
     stage(0, tl.z0 - 1);
     stage(1, tl.z0);
     stage(2, tl.z0 + 1);
@@ -571,7 +590,7 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
                     nw[0] -= T(wg(i) * CX[i]); nw[1] -= T(wg(i) * CY[i]); nw[2] -= T(wg(i) * CZ[i]);
                 }
                 const T nn = dev_sqrt(nw[0] * nw[0] + nw[1] * nw[1] + nw[2] * nw[2]);
-                const T inn = nn > T(0) ? T(1) / nn : T(0);
+                const T inn = nn > T(0) ? dev_div(T(1), nn) : T(0);
                 nw[0] *= inn; nw[1] *= inn; nw[2] *= inn;
             }
             gx = gy = gz = lap = T(0);
@@ -582,7 +601,7 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
             const T ng = nw[0] * g0[0] + nw[1] * g0[1] + nw[2] * g0[2];
             T gt[3] = {g0[0] - nw[0] * ng, g0[1] - nw[1] * ng, g0[2] - nw[2] * ng};
             const T tnn = dev_sqrt(gt[0] * gt[0] + gt[1] * gt[1] + gt[2] * gt[2]);
-            const T itn = T(1) / (tnn + ph[PI_EPS]);
+            const T itn = dev_div(T(1), tnn + ph[PI_EPS]);
             gt[0] *= itn; gt[1] *= itn; gt[2] *= itn;
             T a = T(2) * pc - T(1);
             a = a > T(1) - ph[PI_CLAMP_A] ? T(1) - ph[PI_CLAMP_A] : a;
@@ -607,11 +626,15 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
                 const int cx = CX[i], cy = CY[i], cz = CZ[i];
                 const int sl = cz < 0 ? sm : (cz > 0 ? sp : s0);
                 const int mat = flag_sub(s_flag[sl][c0 + cy * LW + cx]);
-                const T ct = (T)D->cos_t[mat], sn = (T)D->sin_t[mat];
+                const T ct = s_cs[0][mat], sn = s_cs[1][mat];
                 const T d = -ct * cdot(i, nw[0], nw[1], nw[2]) + sn * cdot(i, gt[0], gt[1], gt[2]);
+                // tanh(artanh(a) + 2d/W) by the addition theorem: phi_s,i is
+                // exactly phi(x) where d_i = 0 (a link along the normal of a
+                // 90-degree wall), so the Laplacian there is exactly zero as
+                // in the FP64 model and the sign term of the mobility
+                // correction does not flip on rounding noise
                 const T t = dev_tanh(k2W * d);
-                // tanh(artanh(a) + 2d/W) by the addition theorem
-                T ps = T(0.5) * (T(1) + (a + t) / (T(1) + a * t));
+                T ps = T(0.5) * (T(1) + dev_div(a + t, T(1) + a * t));
                 if (hyst) {
                     T* hp = hist + (int64_t)(i - 1) * hstride + hslot;
                     if (record) {
@@ -667,7 +690,7 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
                 if (CX[i] * CZ[i]) m[4] += T(CX[i] * CZ[i]) * ev;
                 if (CY[i] * CZ[i]) m[5] += T(CY[i] * CZ[i]) * ev;
             }
-            const T irho = T(1) / st.rho;
+            const T irho = dev_div(T(1), st.rho);
             st.u[0] = (j[0] + T(0.5) * (mu * st.grad[0] + ph[PI_FX])) * irho;
             st.u[1] = (j[1] + T(0.5) * (mu * st.grad[1] + ph[PI_FY])) * irho;
             st.u[2] = (j[2] + T(0.5) * (mu * st.grad[2] + ph[PI_FZ])) * irho;
@@ -744,10 +767,10 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
             }
             st.trPi = Tg * (st.Pi[0] + st.Pi[1] + st.Pi[2]);
             T Fm;
-            if (ph.mix) Fm = T(0.5) * (dev_tanh((pb - ph[PI_MIX_PHI]) * ph[PI_MIX_INVW]) + T(1));
+            if (ph.mix) Fm = half_tanh1((pb - ph[PI_MIX_PHI]) * ph[PI_MIX_INVW]);
             else Fm = pb;
             const T tau = (T(1) - Fm) * ph[PI_TAU_G] + Fm * ph[PI_TAU_L];
-            st.om = (T(1) - T(1) / tau) * i2Tg2;
+            st.om = (T(1) - dev_div(T(1), tau)) * i2Tg2;
         }
         const T sg = ph[PI_SG];
         // ---- sub-voxel walls (MODE_STEP): linear interpolated bounce-back of
@@ -809,7 +832,7 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
                                      st.grad[2] * st.grad[2]);
             T theta = ph[PI_THETA0] * (T(1) - T(4) * (pc - T(0.5)) * (pc - T(0.5)));
             if (ph.mobility_corr) {
-                const T sgn = lap / (fabs(lap) + ph[PI_EPS]);
+                const T sgn = dev_div(lap, fabs(lap) + ph[PI_EPS]);
                 const T y1a = clamp01((pc - ph[PI_MC_PHI_M]) * ph[PI_MC_INVD]);
                 const T y1b = clamp01((T(1) - pc) * ph[PI_MC_INVD]);
                 const T y2a = clamp01(pc * ph[PI_MC_INVD]);
@@ -818,7 +841,7 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
                 const T Y2 = y2a < y2b ? y2a : y2b;
                 theta += ph[PI_MC_K] * gnorm * ((T(1) + sgn) * Y1 + (T(1) - sgn) * Y2);
             }
-            const T ign = theta / (gnorm + ph[PI_EPS]);   // theta n = theta grad / (|grad| + eps)
+            const T ign = dev_div(theta, gnorm + ph[PI_EPS]);   // theta n = theta grad / (|grad| + eps)
             st.tn[0] = st.grad[0] * ign; st.tn[1] = st.grad[1] * ign; st.tn[2] = st.grad[2] * ign;
             const T href = ph[PI_HREF];
             T B[QP];
@@ -886,7 +909,7 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
                             // g*_ibar: even (x, i), odd (x - c_i, ibar)
                             const T fo = PAR == 0 ? back(i, (uint32_t)n)
                                                   : back(OPP[i], nb.at(-CX[i], -CY[i], -CZ[i]));
-                            const T r = T(1) / (T(2) * q);
+                            const T r = dev_div(T(1), T(2) * q);
                             return (fi - m) * r + (T(1) - r) * fo;
                         }
                         const T fin = PAR == 1 ? back(OPP[i], (uint32_t)n)

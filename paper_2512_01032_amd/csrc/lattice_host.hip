@@ -139,6 +139,29 @@ int choose_tz(const lbm_params* p, int tx) {
     return std::min(tz, p->nz);
 }
 
+// Workgroups go to the eight XCDs round-robin (block b to XCD b mod 8), and
+// each XCD has its own L2.  The tile list (x fastest, then y, then z) is cut
+// into eight contiguous segments and interleaved so that XCD k walks segment
+// k in order: tiles that share cache lines (the x-neighbours of a row, whose
+// odd-step accesses straddle the row's tile edges, and the phi halo rows)
+// meet in one L2.  Segment lengths differ by at most one; the longer ones
+// come first, so only the final round has fewer than eight blocks.
+void xcd_order(std::vector<Tile>& t) {
+    constexpr int NX = 8;
+    const int64_t n = (int64_t)t.size();
+    const char* env = getenv("LBM_TILE_ORDER");
+    if (n < 2 * NX || (env && strcmp(env, "spatial") == 0)) return;
+    const int64_t S = (n + NX - 1) / NX, r = n - NX * (S - 1);
+    std::vector<Tile> o;
+    o.reserve((size_t)n);
+    for (int64_t j = 0; j < S; ++j)
+        for (int64_t k = 0; k < NX; ++k) {
+            const int64_t len = S - 1 + (k < r ? 1 : 0), start = k * (S - 1) + std::min<int64_t>(k, r);
+            if (j < len) o.push_back(t[(size_t)(start + j)]);
+        }
+    t.swap(o);
+}
+
 static void face_planes(const lbm_params* p, LatticeLayout* L) {
     int64_t b = 0;
     for (int f = 0; f < 6; ++f) {
@@ -341,9 +364,10 @@ int build_layout(const lbm_params* p, const lbm_geometry* geo, int lat, LatticeL
                 Tile t;
                 memset(&t, 0, sizeof(t));
                 t.lat = lat; t.x0 = x0; t.y0 = y0; t.z0 = z0; t.zn = z1 - z0;
-                t.tile_in_lat = (int)L->tiles.size();
                 L->tiles.push_back(t);
             }
+    xcd_order(L->tiles);
+    for (size_t k = 0; k < L->tiles.size(); ++k) L->tiles[k].tile_in_lat = (int)k;
     layout_offsets(p, (int64_t)L->tiles.size(), (int64_t)L->ghosts.size(), L);
     return LBM_OK;
 }

@@ -40,6 +40,7 @@ int validate_params(const lbm_params* p, const lbm_geometry* geo);
 // Tile width for a lattice of width nx; tile depth for a given tile count target.
 int choose_tx(int nx);
 int choose_tz(const lbm_params* p, int tx);
+void xcd_order(std::vector<Tile>& t);   // XCD-aware launch order of a tile list
 
 // Size of the phase-field lattice (7 or 19).
 inline int phase_q(const lbm_params* p) { return p->q_phase == 19 ? 19 : 7; }
