@@ -90,7 +90,14 @@ __device__ inline Tile load_tile(const Tile* tiles) {
 // reached with the scalar offset (q - group start) * N * sizeof(S) and the
 // per-lane 32-bit byte offset of the node.  Each resource spans at most 4 GiB.
 constexpr int BUF_FLAGS = 0x00020000;
-constexpr int AUX_NT = 2;      // non-temporal: every population is touched once per step
+// Cache policy of the population accesses (buffer aux bits; 2 = nt).  The
+// sweep loads and stores with the default (temporal) policy: an odd step's
+// x-shifted stores write partial cache lines at every tile edge, which L2
+// merges with the neighbouring tile's part before write-back only when the
+// lines stay resident (non-temporal stores: sweep 1.28 -> 1.17 ms on the
+// 256 x 256 x 512 duct, FP32; non-temporal loads with temporal stores: 1.34).
+// The phi pass only reads h and streams it non-temporally (0.157 vs 0.177 ms).
+constexpr int AUX_LD = 0, AUX_ST = 0, AUX_PHI = 2;
 template <int Q> struct Split { static constexpr int QS = Q > 10 ? 10 : Q; };
 template <typename S, int Q> struct PopArray {
     __amdgpu_buffer_rsrc_t r0, r1;
@@ -101,34 +108,34 @@ template <typename S, int Q> struct PopArray {
 template <typename S> struct Store;
 template <> struct Store<double> {
     static constexpr bool scaled = false;
-    template <int Q> __device__ static double ld(const PopArray<double, Q>& a, int q, uint32_t n) {
+    template <int Q, int AUX = AUX_LD> __device__ static double ld(const PopArray<double, Q>& a, int q, uint32_t n) {
         typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-        const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(a.rs(q), n * 8u, a.so(q), AUX_NT);
+        const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(a.rs(q), n * 8u, a.so(q), AUX);
         return __builtin_bit_cast(double, v);
     }
     template <int Q> __device__ static void st(const PopArray<double, Q>& a, int q, uint32_t n, double v) {
         typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), a.rs(q), n * 8u, a.so(q), AUX_NT);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), a.rs(q), n * 8u, a.so(q), AUX_ST);
     }
 };
 template <> struct Store<float> {
     static constexpr bool scaled = false;
-    template <int Q> __device__ static float ld(const PopArray<float, Q>& a, int q, uint32_t n) {
-        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(a.rs(q), n * 4u, a.so(q), AUX_NT));
+    template <int Q, int AUX = AUX_LD> __device__ static float ld(const PopArray<float, Q>& a, int q, uint32_t n) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(a.rs(q), n * 4u, a.so(q), AUX));
     }
     template <int Q> __device__ static void st(const PopArray<float, Q>& a, int q, uint32_t n, float v) {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), a.rs(q), n * 4u, a.so(q), AUX_NT);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), a.rs(q), n * 4u, a.so(q), AUX_ST);
     }
 };
 template <> struct Store<_Float16> {
     static constexpr bool scaled = true;
-    template <int Q> __device__ static float ld(const PopArray<_Float16, Q>& a, int q, uint32_t n) {
-        const uint16_t b = __builtin_amdgcn_raw_buffer_load_b16(a.rs(q), n * 2u, a.so(q), AUX_NT);
+    template <int Q, int AUX = AUX_LD> __device__ static float ld(const PopArray<_Float16, Q>& a, int q, uint32_t n) {
+        const uint16_t b = __builtin_amdgcn_raw_buffer_load_b16(a.rs(q), n * 2u, a.so(q), AUX);
         return (float)__builtin_bit_cast(_Float16, b);
     }
     template <int Q> __device__ static void st(const PopArray<_Float16, Q>& a, int q, uint32_t n, float v) {
         const _Float16 hv = (_Float16)v;   // round to nearest even
-        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, hv), a.rs(q), n * 2u, a.so(q), AUX_NT);
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, hv), a.rs(q), n * 2u, a.so(q), AUX_ST);
     }
 };
 template <typename S, int Q> __device__ inline PopArray<S, Q> pop_array(void* base, int64_t N) {
@@ -208,18 +215,18 @@ struct Nbr {
 // ------------------------------------------------------- AA population I/O
 // Deviations d_i of the populations f_i(x) entering node n's collision at a
 // step of parity PAR.  solid: link bits of solid neighbours.
-template <typename T, typename S, int Q, int PAR>
+template <typename T, typename S, int Q, int PAR, int AUX = AUX_LD>
 __device__ inline void read_pops(const PopArray<S, Q>& a, uint32_t n, const Nbr& nb,
                                  uint32_t solid, T inv_scale, T* d) {
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        if (PAR == 0 || i == 0) d[i] = (T)Store<S>::ld(a, i, n);
-        else d[i] = (T)Store<S>::ld(a, OPP[i], nb.at(-CX[i], -CY[i], -CZ[i]));
+        if (PAR == 0 || i == 0) d[i] = (T)Store<S>::template ld<Q, AUX>(a, i, n);
+        else d[i] = (T)Store<S>::template ld<Q, AUX>(a, OPP[i], nb.at(-CX[i], -CY[i], -CZ[i]));
     }
     if (PAR == 1 && solid) {
 #pragma unroll
         for (int i = 1; i < Q; ++i)
-            if ((solid >> OPP[i]) & 1u) d[i] = (T)Store<S>::ld(a, i, n);   // x - c_i solid
+            if ((solid >> OPP[i]) & 1u) d[i] = (T)Store<S>::template ld<Q, AUX>(a, i, n);   // x - c_i solid
     }
     if (Store<S>::scaled) {
 #pragma unroll
@@ -273,7 +280,7 @@ __device__ inline T phase_sum(const PopArray<SH, QP>& h, const uint8_t* flg, con
     Nbr nb;
     nb.init(x, y, z, nx, ny, nz);
     T d[QP];
-    read_pops<T, SH, QP, PAR>(h, (uint32_t)n, nb, solid, ph[PI_INV_SH], d);
+    read_pops<T, SH, QP, PAR, AUX_PHI>(h, (uint32_t)n, nb, solid, ph[PI_INV_SH], d);
     T s = T(0);
 #pragma unroll
     for (int i = 0; i < QP; ++i) s += d[i];
