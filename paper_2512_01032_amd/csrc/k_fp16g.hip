@@ -11,7 +11,7 @@ hipError_t launch_sweep_fp16g(int qp, int mode, int tx, int parity, Desc* d, con
 
 hipError_t launch_phi_fp16g(int qp, int parity, const Desc* d, const Tile* tiles, int ntiles,
                         hipStream_t s, int force) {
-    return launch_phi_storage<float, float>(qp, parity, d, tiles, ntiles, s, force);
+    return launch_phi_storage<float, float, _Float16>(qp, parity, d, tiles, ntiles, s, force);
 }
 
 hipError_t launch_restore_fp16g(int qp, int parity, const Desc* d, const Tile* tiles, int ntiles,

@@ -11,7 +11,7 @@ hipError_t launch_sweep_fp64(int qp, int mode, int tx, int parity, Desc* d, cons
 
 hipError_t launch_phi_fp64(int qp, int parity, const Desc* d, const Tile* tiles, int ntiles,
                         hipStream_t s, int force) {
-    return launch_phi_storage<double, double>(qp, parity, d, tiles, ntiles, s, force);
+    return launch_phi_storage<double, double, double>(qp, parity, d, tiles, ntiles, s, force);
 }
 
 hipError_t launch_restore_fp64(int qp, int parity, const Desc* d, const Tile* tiles, int ntiles,

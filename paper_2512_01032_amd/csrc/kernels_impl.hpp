@@ -85,10 +85,12 @@ __device__ inline Tile load_tile(const Tile* tiles) {
 }
 
 // --------------------------------------------------------------- storage
-// Population array [Q][N] of storage type S behind raw buffer resources: the
-// directions [0, QS) share resource r0 and [QS, Q) resource r1; direction q is
-// reached with the scalar offset (q - group start) * N * sizeof(S) and the
-// per-lane 32-bit byte offset of the node.  Each resource spans at most 4 GiB.
+// Populations in the blocked layout of pop_layout (pflbm.hpp): group r is a
+// raw buffer resource of Np * pb bytes; direction u (h first, then g) sits at
+// the scalar offset 64 (prefix(u) - prefix(first direction of its group)) of
+// every block, and a node at the per-lane byte offset
+//   (p / 64) 64 pb + (p % 64) sizeof(S),   p = x + nxp (y + ny z)
+// (Nbr below), so both offsets fit 32 bits.
 constexpr int BUF_FLAGS = 0x00020000;
 // Cache policy of the population accesses (buffer aux bits; 2 = nt).  The
 // sweep loads and stores with the default (temporal) policy: an odd step's
@@ -98,57 +100,93 @@ constexpr int BUF_FLAGS = 0x00020000;
 // 256 x 256 x 512 duct, FP32; non-temporal loads with temporal stores: 1.34).
 // The phi pass only reads h and streams it non-temporally (0.157 vs 0.177 ms).
 constexpr int AUX_LD = 0, AUX_ST = 0, AUX_PHI = 2;
-template <int Q> struct Split { static constexpr int QS = Q > 10 ? 10 : Q; };
-template <typename S, int Q> struct PopArray {
+// layout constants of a (phase lattice, storage) pair
+template <typename SH, typename SG, int QP> struct Lay {
+    static constexpr PopLayout L = pop_layout(QP, (int)sizeof(SH), (int)sizeof(SG));
+    static constexpr int G = L.G, K = L.k, PB = L.pb, BLK = 64 * L.pb;
+    static constexpr int SZH = (int)sizeof(SH), SZG = (int)sizeof(SG);
+    static constexpr int prefix(int u) { return pop_prefix(u, QP, SZH, SZG); }
+};
+// one family of populations (h: U0 = 0, Q = QP; g: U0 = QP, Q = 19)
+template <typename S_, int Q_, int U0, typename LAY> struct PopArray {
+    typedef S_ S;
+    static constexpr int Q = Q_;
+    static constexpr bool IS_G = U0 > 0;
     __amdgpu_buffer_rsrc_t r0, r1;
-    uint32_t stride;           // N * sizeof(S)
-    __device__ __amdgpu_buffer_rsrc_t rs(int q) const { return q < Split<Q>::QS ? r0 : r1; }
-    __device__ uint32_t so(int q) const { return (uint32_t)(q < Split<Q>::QS ? q : q - Split<Q>::QS) * stride; }
+    __device__ __amdgpu_buffer_rsrc_t rs(int q) const { return U0 + q < LAY::K ? r0 : r1; }
+    __device__ static constexpr uint32_t so(int q) {
+        return (uint32_t)(64 * (LAY::prefix(U0 + q) - (U0 + q < LAY::K ? 0 : LAY::prefix(LAY::K))));
+    }
+    // directions q and r live in the same group (one resource)
+    __device__ static constexpr bool same(int q, int r) { return (U0 + q < LAY::K) == (U0 + r < LAY::K); }
+    __device__ static constexpr uint32_t lo(int q, int r) { return so(q) < so(r) ? so(q) : so(r); }
 };
 template <typename S> struct Store;
 template <> struct Store<double> {
     static constexpr bool scaled = false;
-    template <int Q, int AUX = AUX_LD> __device__ static double ld(const PopArray<double, Q>& a, int q, uint32_t n) {
+    template <int AUX = AUX_LD, typename PA> __device__ static double ld(const PA& a, int q, uint32_t off) {
         typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-        const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(a.rs(q), n * 8u, a.so(q), AUX);
+        const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(a.rs(q), off, a.so(q), AUX);
         return __builtin_bit_cast(double, v);
     }
-    template <int Q> __device__ static void st(const PopArray<double, Q>& a, int q, uint32_t n, double v) {
+    template <typename PA> __device__ static void st(const PA& a, int q, uint32_t off, double v) {
         typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), a.rs(q), n * 8u, a.so(q), AUX_ST);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), a.rs(q), off, a.so(q), AUX_ST);
+    }
+    template <int AUX = AUX_LD, typename PA> __device__ static double ldx(const PA& a, int q, uint32_t voff, uint32_t soff) {
+        typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(a.rs(q), voff, soff, AUX));
+    }
+    template <typename PA> __device__ static void stx(const PA& a, int q, uint32_t voff, uint32_t soff, double v) {
+        typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), a.rs(q), voff, soff, AUX_ST);
     }
 };
 template <> struct Store<float> {
     static constexpr bool scaled = false;
-    template <int Q, int AUX = AUX_LD> __device__ static float ld(const PopArray<float, Q>& a, int q, uint32_t n) {
-        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(a.rs(q), n * 4u, a.so(q), AUX));
+    template <int AUX = AUX_LD, typename PA> __device__ static float ld(const PA& a, int q, uint32_t off) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(a.rs(q), off, a.so(q), AUX));
     }
-    template <int Q> __device__ static void st(const PopArray<float, Q>& a, int q, uint32_t n, float v) {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), a.rs(q), n * 4u, a.so(q), AUX_ST);
+    template <typename PA> __device__ static void st(const PA& a, int q, uint32_t off, float v) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), a.rs(q), off, a.so(q), AUX_ST);
+    }
+    template <int AUX = AUX_LD, typename PA> __device__ static float ldx(const PA& a, int q, uint32_t voff, uint32_t soff) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(a.rs(q), voff, soff, AUX));
+    }
+    template <typename PA> __device__ static void stx(const PA& a, int q, uint32_t voff, uint32_t soff, float v) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), a.rs(q), voff, soff, AUX_ST);
     }
 };
 template <> struct Store<_Float16> {
     static constexpr bool scaled = true;
-    template <int Q, int AUX = AUX_LD> __device__ static float ld(const PopArray<_Float16, Q>& a, int q, uint32_t n) {
-        const uint16_t b = __builtin_amdgcn_raw_buffer_load_b16(a.rs(q), n * 2u, a.so(q), AUX);
+    template <int AUX = AUX_LD, typename PA> __device__ static float ld(const PA& a, int q, uint32_t off) {
+        const uint16_t b = __builtin_amdgcn_raw_buffer_load_b16(a.rs(q), off, a.so(q), AUX);
         return (float)__builtin_bit_cast(_Float16, b);
     }
-    template <int Q> __device__ static void st(const PopArray<_Float16, Q>& a, int q, uint32_t n, float v) {
+    template <typename PA> __device__ static void st(const PA& a, int q, uint32_t off, float v) {
         const _Float16 hv = (_Float16)v;   // round to nearest even
-        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, hv), a.rs(q), n * 2u, a.so(q), AUX_ST);
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, hv), a.rs(q), off, a.so(q), AUX_ST);
+    }
+    template <int AUX = AUX_LD, typename PA> __device__ static float ldx(const PA& a, int q, uint32_t voff, uint32_t soff) {
+        const uint16_t b = __builtin_amdgcn_raw_buffer_load_b16(a.rs(q), voff, soff, AUX);
+        return (float)__builtin_bit_cast(_Float16, b);
+    }
+    template <typename PA> __device__ static void stx(const PA& a, int q, uint32_t voff, uint32_t soff, float v) {
+        const _Float16 hv = (_Float16)v;
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, hv), a.rs(q), voff, soff, AUX_ST);
     }
 };
-template <typename S, int Q> __device__ inline PopArray<S, Q> pop_array(void* base, int64_t N) {
-    PopArray<S, Q> a;
-    char* b = unip((char*)base);
-    const uint32_t stride = (uint32_t)uni((int64_t)(N * (int64_t)sizeof(S)));
-    constexpr int QS = Split<Q>::QS;
-    a.stride = stride;
-    a.r0 = __builtin_amdgcn_make_buffer_rsrc(b, (short)0, (int)(stride * (uint32_t)QS), BUF_FLAGS);
-    a.r1 = __builtin_amdgcn_make_buffer_rsrc(b + (size_t)QS * stride, (short)0,
-                                             (int)(stride * (uint32_t)(Q - QS > 0 ? Q - QS : 1)), BUF_FLAGS);
+// the h (U0 = 0) or g (U0 = QP) family of descriptor D
+template <typename S, int Q, int U0, typename LAY>
+__device__ inline PopArray<S, Q, U0, LAY> pop_array(const Desc* D) {
+    PopArray<S, Q, U0, LAY> a;
+    const uint32_t bytes = (uint32_t)uni((int64_t)(D->Np * (int64_t)LAY::PB));
+    a.r0 = __builtin_amdgcn_make_buffer_rsrc(unip((char*)D->pops[0]), (short)0, (int)bytes, BUF_FLAGS);
+    a.r1 = __builtin_amdgcn_make_buffer_rsrc(unip((char*)D->pops[1]), (short)0, (int)bytes, BUF_FLAGS);
     return a;
 }
+#define PFLBM_HB(T_SH, T_SG, QP_) PopArray<T_SH, QP_, 0, Lay<T_SH, T_SG, QP_>>
+#define PFLBM_GB(T_SH, T_SG, QP_) PopArray<T_SG, QG, QP_, Lay<T_SH, T_SG, QP_>>
 
 // ----------------------------------------------------------- parameters
 // Derived constants come precomputed in the compute precision (Desc::pf for
@@ -195,38 +233,67 @@ __device__ inline int wrapc(int v, int n) {
     return v < 0 ? v + n : v;
 }
 
-// Neighbour node indices of (x, y, z) with periodic wrap:
-// at(cx, cy, cz) = X[cx+1] + Y[cy+1] + Z[cz+1].
+// Byte offsets of the 27 nodes around (x, y, z), periodic wrap, in the
+// blocked population layout: at<IS_G>(cx, cy, cz) = A[cx+1] + BY[cy+1] +
+// BZ[cz+1], with A = (x' / 64) 64 pb + (x' % 64) sizeof(S) for the wrapped x'
+// (AH for h, AG for g: the same registers when h and g share their type),
+// BY = y' (nxp / 64) 64 pb, BZ = z' ny (nxp / 64) 64 pb.
 struct Nbr {
-    int X[3], Y[3], Z[3];
-    __device__ void init(int x, int y, int z, int nx, int ny, int nz) {
-        X[0] = x == 0 ? nx - 1 : x - 1; X[1] = x; X[2] = x == nx - 1 ? 0 : x + 1;
+    uint32_t AH[3], AG[3], BY[3], BZ[3];
+    template <typename LAY>
+    __device__ void init(int x, int y, int z, int nx, int ny, int nz, int nxp) {
+        const int xs[3] = {x == 0 ? nx - 1 : x - 1, x, x == nx - 1 ? 0 : x + 1};
         const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
         const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
-        Y[0] = ym * nx; Y[1] = y * nx; Y[2] = yp * nx;
-        const int nxy = nx * ny;
-        Z[0] = zm * nxy; Z[1] = z * nxy; Z[2] = zp * nxy;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const uint32_t b = (uint32_t)(xs[c] >> 6) * (uint32_t)LAY::BLK, l = (uint32_t)(xs[c] & 63);
+            AH[c] = b + l * (uint32_t)LAY::SZH;
+            AG[c] = b + l * (uint32_t)LAY::SZG;
+        }
+        const uint32_t row = (uint32_t)(nxp >> 6) * (uint32_t)LAY::BLK;
+        BY[0] = (uint32_t)ym * row; BY[1] = (uint32_t)y * row; BY[2] = (uint32_t)yp * row;
+        const uint32_t plane = (uint32_t)ny * row;
+        BZ[0] = (uint32_t)zm * plane; BZ[1] = (uint32_t)z * plane; BZ[2] = (uint32_t)zp * plane;
     }
-    __device__ uint32_t at(int cx, int cy, int cz) const {
-        return (uint32_t)(X[cx + 1] + Y[cy + 1] + Z[cz + 1]);
+    template <bool IS_G> __device__ uint32_t at(int cx, int cy, int cz) const {
+        return (IS_G ? AG[cx + 1] : AH[cx + 1]) + BY[cy + 1] + BZ[cz + 1];
     }
+    template <bool IS_G> __device__ uint32_t own() const { return at<IS_G>(0, 0, 0); }
 };
 
 // ------------------------------------------------------- AA population I/O
-// Deviations d_i of the populations f_i(x) entering node n's collision at a
-// step of parity PAR.  solid: link bits of solid neighbours.
-template <typename T, typename S, int Q, int PAR, int AUX = AUX_LD>
-__device__ inline void read_pops(const PopArray<S, Q>& a, uint32_t n, const Nbr& nb,
-                                 uint32_t solid, T inv_scale, T* d) {
+// At an odd step a wall link changes which slot a node reads or writes: the
+// slot of the neighbour (direction a at the neighbour's offset) or its own
+// slot (direction b at its own offset).  When a and b share a resource one
+// access serves both cases: its scalar offset is the smaller of the two
+// directions' offsets and each lane adds the rest to its own address.
+template <typename PA>
+__device__ inline uint32_t sel_off(int a, uint32_t off_a, int b, uint32_t off_b, bool use_b) {
+    const uint32_t lo = PA::lo(a, b);
+    return use_b ? off_b + (PA::so(b) - lo) : off_a + (PA::so(a) - lo);
+}
+
+// Deviations d_i of the populations f_i(x) entering the node's collision at a
+// step of parity PAR.  solid: link bits of solid neighbours.  Odd step:
+// f_i(x) is in (x - c_i, opp(i)), or in (x, i) when x - c_i is solid.
+template <typename T, int PAR, int AUX = AUX_LD, typename PA>
+__device__ inline void read_pops(const PA& a, const Nbr& nb, uint32_t solid, T inv_scale, T* d) {
+    typedef typename PA::S S;
+    constexpr int Q = PA::Q;
+    constexpr bool G = PA::IS_G;
+    const uint32_t n = nb.own<G>();
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        if (PAR == 0 || i == 0) d[i] = (T)Store<S>::template ld<Q, AUX>(a, i, n);
-        else d[i] = (T)Store<S>::template ld<Q, AUX>(a, OPP[i], nb.at(-CX[i], -CY[i], -CZ[i]));
-    }
-    if (PAR == 1 && solid) {
-#pragma unroll
-        for (int i = 1; i < Q; ++i)
-            if ((solid >> OPP[i]) & 1u) d[i] = (T)Store<S>::template ld<Q, AUX>(a, i, n);   // x - c_i solid
+        if (PAR == 0 || i == 0) {
+            d[i] = (T)Store<S>::template ld<AUX>(a, i, n);
+        } else if (PA::same(OPP[i], i)) {
+            const uint32_t off = sel_off<PA>(OPP[i], nb.at<G>(-CX[i], -CY[i], -CZ[i]), i, n, (solid >> OPP[i]) & 1u);
+            d[i] = (T)Store<S>::template ldx<AUX>(a, i, off, PA::lo(OPP[i], i));
+        } else {
+            d[i] = (T)Store<S>::template ld<AUX>(a, OPP[i], nb.at<G>(-CX[i], -CY[i], -CZ[i]));
+            if ((solid >> OPP[i]) & 1u) d[i] = (T)Store<S>::template ld<AUX>(a, i, n);
+        }
     }
     if (Store<S>::scaled) {
 #pragma unroll
@@ -234,62 +301,81 @@ __device__ inline void read_pops(const PopArray<S, Q>& a, uint32_t n, const Nbr&
     }
 }
 
-// Post-collision deviations of node n at a step of parity PAR.
-template <typename T, typename S, int Q, int PAR>
-__device__ inline void write_pops(const PopArray<S, Q>& a, uint32_t n, const Nbr& nb,
-                                  uint32_t solid, T scale, const T* d) {
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const T v = Store<S>::scaled ? d[i] * scale : d[i];
-        if (PAR == 0 || i == 0) Store<S>::st(a, OPP[i], n, v);
-        else Store<S>::st(a, i, nb.at(CX[i], CY[i], CZ[i]), v);
-    }
-    if (PAR == 1 && solid) {
-#pragma unroll
-        for (int i = 1; i < Q; ++i)
-            if ((solid >> i) & 1u)                                           // x + c_i solid
-                Store<S>::st(a, OPP[i], n, Store<S>::scaled ? d[i] * scale : d[i]);
+// Store of the post-collision value v of direction i (i > 0) at a step of
+// parity PAR: even (x, opp(i)); odd (x + c_i, i), or (x, opp(i)) when x + c_i
+// is solid (half-way bounce-back).
+template <int PAR, typename PA, typename V>
+__device__ inline void put_pop(const PA& a, const Nbr& nb, uint32_t solid, int i, V v) {
+    typedef typename PA::S S;
+    constexpr bool G = PA::IS_G;
+    const uint32_t n = nb.own<G>();
+    if (PAR == 0 || i == 0) {
+        Store<S>::st(a, OPP[i], n, v);
+    } else if (PA::same(i, OPP[i])) {
+        const uint32_t off = sel_off<PA>(i, nb.at<G>(CX[i], CY[i], CZ[i]), OPP[i], n, (solid >> i) & 1u);
+        Store<S>::stx(a, i, off, PA::lo(i, OPP[i]), v);
+    } else {
+        Store<S>::st(a, i, nb.at<G>(CX[i], CY[i], CZ[i]), v);
+        if ((solid >> i) & 1u) Store<S>::st(a, OPP[i], n, v);
     }
 }
 
-// f_i(x) into the slots a step of parity PAR reads (initialisation, restore).
-template <typename T, typename S, int Q, int PAR>
-__device__ inline void place_pops(const PopArray<S, Q>& a, uint32_t n, const Nbr& nb,
-                                  uint32_t solid, T scale, const T* d) {
+// Post-collision deviations of the node at a step of parity PAR.
+template <typename T, int PAR, typename PA>
+__device__ inline void write_pops(const PA& a, const Nbr& nb, uint32_t solid, T scale, const T* d) {
+    typedef typename PA::S S;
+    constexpr int Q = PA::Q;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const T v = Store<S>::scaled ? d[i] * scale : d[i];
-        if (PAR == 0 || i == 0) Store<S>::st(a, i, n, v);
-        else Store<S>::st(a, OPP[i], nb.at(-CX[i], -CY[i], -CZ[i]), v);
+    for (int i = 0; i < Q; ++i) put_pop<PAR>(a, nb, solid, i, Store<S>::scaled ? d[i] * scale : d[i]);
+}
+
+// f_i(x) into the slot a step of parity PAR reads it from (initialisation,
+// restore): even (x, i); odd (x - c_i, opp(i)), or (x, i) when x - c_i is solid.
+template <int PAR, typename PA, typename V>
+__device__ inline void place_pop(const PA& a, const Nbr& nb, uint32_t solid, int i, V v) {
+    typedef typename PA::S S;
+    constexpr bool G = PA::IS_G;
+    const uint32_t n = nb.own<G>();
+    if (PAR == 0 || i == 0) {
+        Store<S>::st(a, i, n, v);
+    } else if (PA::same(OPP[i], i)) {
+        const uint32_t off = sel_off<PA>(OPP[i], nb.at<G>(-CX[i], -CY[i], -CZ[i]), i, n, (solid >> OPP[i]) & 1u);
+        Store<S>::stx(a, i, off, PA::lo(OPP[i], i), v);
+    } else {
+        Store<S>::st(a, OPP[i], nb.at<G>(-CX[i], -CY[i], -CZ[i]), v);
+        if ((solid >> OPP[i]) & 1u) Store<S>::st(a, i, n, v);
     }
-    if (PAR == 1 && solid) {
+}
+template <typename T, int PAR, typename PA>
+__device__ inline void place_pops(const PA& a, const Nbr& nb, uint32_t solid, T scale, const T* d) {
+    typedef typename PA::S S;
+    constexpr int Q = PA::Q;
 #pragma unroll
-        for (int i = 1; i < Q; ++i)
-            if ((solid >> OPP[i]) & 1u)
-                Store<S>::st(a, i, n, Store<S>::scaled ? d[i] * scale : d[i]);
-    }
+    for (int i = 0; i < Q; ++i) place_pop<PAR>(a, nb, solid, i, Store<S>::scaled ? d[i] * scale : d[i]);
 }
 
 // ------------------------------------------------------------------ phi pass
-template <typename T, typename SH, int PAR, int QP>
-__device__ inline T phase_sum(const PopArray<SH, QP>& h, const uint8_t* flg, const uint32_t* lnk,
-                              int n, int x, int y, int z, int nx, int ny, int nz,
+template <typename T, int PAR, typename LAY, typename PA>
+__device__ inline T phase_sum(const PA& h, const uint8_t* flg, const uint32_t* lnk,
+                              int n, int x, int y, int z, int nx, int ny, int nz, int nxp,
                               const Phys<T>& ph) {
+    constexpr int QP = PA::Q;
     const uint8_t f = flg[n];
     const uint32_t solid = (PAR == 1 && (f & F_NEAR_WALL)) ? (lnk[n] & SOLID_MASK) : 0u;
     Nbr nb;
-    nb.init(x, y, z, nx, ny, nz);
+    nb.init<LAY>(x, y, z, nx, ny, nz, nxp);
     T d[QP];
-    read_pops<T, SH, QP, PAR, AUX_PHI>(h, (uint32_t)n, nb, solid, ph[PI_INV_SH], d);
+    read_pops<T, PAR, AUX_PHI>(h, nb, solid, ph[PI_INV_SH], d);
     T s = T(0);
 #pragma unroll
     for (int i = 0; i < QP; ++i) s += d[i];
     return ph[PI_HREF] + s;
 }
 
-template <typename T, typename SH, int PAR, int QP>
+template <typename T, typename SH, typename SG, int PAR, int QP>
 __global__ void __launch_bounds__(NTHREADS)
 phi_kernel(const Desc* __restrict__ descs, const Tile* __restrict__ tiles, int force) {
+    typedef Lay<SH, SG, QP> LAYT;
     const Tile tl = load_tile(tiles);
     const Desc* D = descs + tl.lat;
     const int64_t step = uni(D->step);
@@ -300,7 +386,8 @@ phi_kernel(const Desc* __restrict__ descs, const Tile* __restrict__ tiles, int f
     if (x >= nx || y >= ny) return;
     Phys<T> ph;
     ph.load(D);
-    const PopArray<SH, QP> h = pop_array<SH, QP>(D->h, uni(D->N));
+    const auto h = pop_array<SH, QP, 0, LAYT>(D);
+    const int nxp = uni(D->nxp);
     const uint8_t* __restrict__ flg = unip(D->flag);
     const uint32_t* __restrict__ lnk = unip(D->link);
     T* __restrict__ phi = unip((T*)D->phi);
@@ -311,7 +398,7 @@ phi_kernel(const Desc* __restrict__ descs, const Tile* __restrict__ tiles, int f
         const int kind = flag_kind(f);
         T v = T(0);
         if (kind == KIND_FLUID) {
-            v = phase_sum<T, SH, PAR, QP>(h, flg, lnk, n, x, y, z, nx, ny, nz, ph);
+            v = phase_sum<T, PAR, LAYT>(h, flg, lnk, n, x, y, z, nx, ny, nz, nxp, ph);
         } else if (kind == KIND_GHOST) {
             // owner = one step inward along the face normal
             const int face = flag_sub(f);
@@ -319,7 +406,7 @@ phi_kernel(const Desc* __restrict__ descs, const Tile* __restrict__ tiles, int f
             int ox = x, oy = y, oz = z;
             if (ax == 0) ox += sg; else if (ax == 1) oy += sg; else oz += sg;
             const int o = ox + nx * (oy + ny * oz);
-            v = phase_sum<T, SH, PAR, QP>(h, flg, lnk, o, ox, oy, oz, nx, ny, nz, ph);
+            v = phase_sum<T, PAR, LAYT>(h, flg, lnk, o, ox, oy, oz, nx, ny, nz, nxp, ph);
         }
         phi[n] = v;
     }
@@ -424,13 +511,10 @@ __device__ inline void h_eq_pair(int i, const NodeState<T>& s, T href, T& hp, T&
     hm = w * (e - o);
 }
 
-#ifndef SWEEP_WAVES_PER_EU
-#define SWEEP_WAVES_PER_EU 1
-#endif
 // SV: instance with the interpolated bounce-back of sub-voxel walls (step
 // mode only; lattices without sub-voxel walls keep half-way walls in it).
 template <typename T, typename SH, typename SG, int MODE, bool DIAG, int TX, int PAR, int QP, bool SV = false>
-__global__ void __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(SWEEP_WAVES_PER_EU)))
+__global__ void __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(1)))
 sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut ro, InitIn in) {
     // LDS ring of phi and flags: each plane holds the tile plus a one-node
     // halo, LN cells, staged NST cells per thread
@@ -462,8 +546,10 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
     const T* __restrict__ phig = unip((const T*)D->phi);
     const uint8_t* __restrict__ flg = unip(D->flag);
     const uint32_t* __restrict__ lnk = unip(D->link);
-    const PopArray<SH, QP> hb = pop_array<SH, QP>(D->h, N);
-    const PopArray<SG, QG> gb = pop_array<SG, QG>(D->g, N);
+    typedef Lay<SH, SG, QP> LAYT;
+    const auto hb = pop_array<SH, QP, 0, LAYT>(D);
+    const auto gb = pop_array<SG, QG, QP, LAYT>(D);
+    const int nxp = uni(D->nxp);
     const T Tg = T(TGc);
     const T iTg = T(3), i2Tg2 = T(4.5);
     const T rdif = ph[PI_RDIF];
@@ -545,7 +631,8 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
         const uint32_t links = (f & (F_NEAR_WALL | F_OWNER)) ? lnk[n] : 0u;
         const uint32_t solid = links & SOLID_MASK;
         Nbr nb;
-        nb.init(x, y, z, nx, ny, nz);
+        nb.init<LAYT>(x, y, z, nx, ny, nz, nxp);
+        const uint32_t gown = nb.own<true>();   // the node's own g slots
         NodeState<T> st;
         const T pc = s_phi[s0][c0];
         st.pc = pc;
@@ -679,7 +766,7 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
             st.pdev = in.P ? (T)in.P[n] * iTg - ph[PI_GREF] : ph[PI_PREF_DEV];
         } else {
             T dg[QG];
-            read_pops<T, SG, QG, PAR>(gb, (uint32_t)n, nb, solid, ph[PI_INV_SG], dg);
+            read_pops<T, PAR>(gb, nb, solid, ph[PI_INV_SG], dg);
             // pairs (i, opp(i)): even part feeds mass and second moments, odd
             // part the momentum; u first (it needs only g and phi), then P
             T s = dg[0], j[3] = {T(0), T(0), T(0)};
@@ -717,7 +804,7 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
             if (ro.u) { ro.u[n] = (double)st.u[0]; ro.u[N + n] = (double)st.u[1]; ro.u[2 * N + n] = (double)st.u[2]; }
             if (ro.pops) {
                 T dh[QP];
-                read_pops<T, SH, QP, PAR>(hb, (uint32_t)n, nb, solid, ph[PI_INV_SH], dh);
+                read_pops<T, PAR>(hb, nb, solid, ph[PI_INV_SH], dh);
                 for (int i = 0; i < QP; ++i)
                     ro.pops[(int64_t)i * N + n] = (double)(T(wp<QP>(i)) * ph[PI_HREF] + dh[i]);
             }
@@ -799,29 +886,51 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
                     const bool si = (solid >> i) & 1u, sj = (solid >> j) & 1u;
                     if (!si && !sj) continue;
                     SG fi_in = SG(0), fj_in = SG(0);
-                    if (si) fi_in = (SG)(sj ? Store<SG>::ld(gb, i, (uint32_t)n)
-                                            : Store<SG>::ld(gb, j, nb.at(-CX[i], -CY[i], -CZ[i])));
-                    if (sj) fj_in = (SG)(si ? Store<SG>::ld(gb, j, (uint32_t)n)
-                                            : Store<SG>::ld(gb, i, nb.at(-CX[j], -CY[j], -CZ[j])));
-                    if (si) Store<SG>::st(gb, j, (uint32_t)n, fi_in);
-                    if (sj) Store<SG>::st(gb, i, (uint32_t)n, fj_in);
+                    if (si) fi_in = (SG)(sj ? Store<SG>::ld(gb, i, gown)
+                                            : Store<SG>::ld(gb, j, nb.at<true>(-CX[i], -CY[i], -CZ[i])));
+                    if (sj) fj_in = (SG)(si ? Store<SG>::ld(gb, j, gown)
+                                            : Store<SG>::ld(gb, i, nb.at<true>(-CX[j], -CY[j], -CZ[j])));
+                    if (si) Store<SG>::st(gb, j, gown, fi_in);
+                    if (sj) Store<SG>::st(gb, i, gown, fj_in);
                 }
             } else {
                 // f_i^in sits in the own slot (x, i); parked in (x + c_i, i)
                 for (int i = 1; i < QG; ++i)
                     if ((solid >> i) & 1u)
-                        Store<SG>::st(gb, i, nb.at(CX[i], CY[i], CZ[i]), Store<SG>::ld(gb, i, (uint32_t)n));
+                        Store<SG>::st(gb, i, nb.at<true>(CX[i], CY[i], CZ[i]), Store<SG>::ld(gb, i, gown));
             }
         }
         // D3Q19 write-back (AA slots of parity PAR)
+        // free-slip band (Sec. III.A): at a wall link the wall moves with the
+        // tangential fluid velocity u_w, and the bounced-back population
+        // loses the moving-wall term 6 w_i rho (c_i . u_w)
+        T uw[3] = {T(0), T(0), T(0)};
+        bool slip = false;
+        if (MODE == MODE_STEP && solid && ph.friction && pc >= ph[PI_SLIP_LO] && pc <= ph[PI_SLIP_HI]) {
+            const T un = nw[0] * st.u[0] + nw[1] * st.u[1] + nw[2] * st.u[2];
+            uw[0] = st.u[0] - nw[0] * un;
+            uw[1] = st.u[1] - nw[1] * un;
+            uw[2] = st.u[2] - nw[2] * un;
+            slip = true;
+        }
+        auto mwall = [&](int i) -> T {
+            const T cuw = T(CX[i]) * uw[0] + T(CY[i]) * uw[1] + T(CZ[i]) * uw[2];
+            return T(6 * wg(i)) * st.rho * cuw;
+        };
+        // write-back: half-way bounce-back at wall links through the slot
+        // choice of put_pop (even: the own slot (x, ibar) anyway; odd: (x, ibar)
+        // instead of the solid node's (x + c_i, i)), with the moving-wall term
+        // applied in registers.  The sub-voxel instance stores every value
+        // at its unbounded AA slot and fixes the wall links afterwards.
         auto put_g = [&](int i, T v) {
+            if (MODE == MODE_STEP && !SV && slip && i > 0 && ((solid >> i) & 1u)) v -= mwall(i);
             const T vs = Store<SG>::scaled ? v * sg : v;
             if (MODE == MODE_STEP) {
-                if (PAR == 0 || i == 0) Store<SG>::st(gb, OPP[i], (uint32_t)n, vs);
-                else Store<SG>::st(gb, i, nb.at(CX[i], CY[i], CZ[i]), vs);
+                if (!SV) put_pop<PAR>(gb, nb, solid, i, vs);
+                else if (PAR == 0 || i == 0) Store<SG>::st(gb, OPP[i], gown, vs);
+                else Store<SG>::st(gb, i, nb.at<true>(CX[i], CY[i], CZ[i]), vs);
             } else {
-                if (PAR == 0 || i == 0) Store<SG>::st(gb, i, (uint32_t)n, vs);
-                else Store<SG>::st(gb, OPP[i], nb.at(-CX[i], -CY[i], -CZ[i]), vs);
+                place_pop<PAR>(gb, nb, solid, i, vs);
             }
         };
         put_g(0, g_out<T, MODE>(0, st, rdif));
@@ -852,7 +961,7 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
             st.tn[0] = st.grad[0] * ign; st.tn[1] = st.grad[1] * ign; st.tn[2] = st.grad[2] * ign;
             const T href = ph[PI_HREF];
             T B[QP];
-            if (MODE == MODE_STEP) read_pops<T, SH, QP, PAR>(hb, (uint32_t)n, nb, solid, ph[PI_INV_SH], B);
+            if (MODE == MODE_STEP) read_pops<T, PAR>(hb, nb, solid, ph[PI_INV_SH], B);
             const T itau_h = ph[PI_ITAU_H];
             {
                 const T heq0 = T(wp<QP>(0)) * ((pc - href) + pc * (-T(i2tp<QP>()) * st.uu));
@@ -870,29 +979,18 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
                     B[i + 1] = hm;
                 }
             }
-            if (MODE == MODE_STEP) write_pops<T, SH, QP, PAR>(hb, (uint32_t)n, nb, solid, ph[PI_SH], B);
-            else place_pops<T, SH, QP, PAR>(hb, (uint32_t)n, nb, solid, ph[PI_SH], B);
+            if (MODE == MODE_STEP) write_pops<T, PAR>(hb, nb, solid, ph[PI_SH], B);
+            else place_pops<T, PAR>(hb, nb, solid, ph[PI_SH], B);
         }
 
-        // ---- solid links (Sec. III.A).  Half-way bounce-back returns g*_i to
-        //      the node's own slot (x, ibar): the even write-back already put
-        //      it there, the odd one into the solid node's slot (x + c_i, i),
-        //      never read.  Inside the free-slip band the wall moves with the
-        //      tangential fluid velocity (moving-wall bounce-back), which
-        //      changes the returned g.  The post-collision values are read
-        //      back from where the write-back stored them (slots only this
-        //      node writes during the step) rather than recomputed.
-        if (solid) {
-            if (MODE == MODE_STEP) {
-                T uw[3] = {T(0), T(0), T(0)};
-                bool slip = false;
-                if (ph.friction && pc >= ph[PI_SLIP_LO] && pc <= ph[PI_SLIP_HI]) {
-                    const T un = nw[0] * st.u[0] + nw[1] * st.u[1] + nw[2] * st.u[2];
-                    uw[0] = st.u[0] - nw[0] * un;
-                    uw[1] = st.u[1] - nw[1] * un;
-                    uw[2] = st.u[2] - nw[2] * un;
-                    slip = true;
-                }
+        // ---- sub-voxel instance: wall links (Sec. III.A).  The value returned
+        //      along ibar goes to the node's own slot (x, ibar): the even
+        //      write-back put g*_i there, the odd one into the solid node's
+        //      slot (x + c_i, i), never read.  The post-collision values are
+        //      read back from where the write-back stored them (slots only
+        //      this node writes during the step) rather than recomputed.
+        if (SV && MODE == MODE_STEP && solid) {
+            {
                 const T isg = ph[PI_INV_SG];
                 auto back = [&](int q, uint32_t node) -> T {
                     const T v = (T)Store<SG>::ld(gb, q, node);
@@ -901,11 +999,10 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
                 if ((SV && svx) || PAR == 1 || slip) {
                     // value returned along ibar for solid link i (reads only)
                     auto wall_value = [&](int i) -> T {
-                        const T cuw = T(CX[i]) * uw[0] + T(CY[i]) * uw[1] + T(CZ[i]) * uw[2];
-                        const T m = T(6 * wg(i)) * st.rho * cuw;     // moving-wall term
+                        const T m = mwall(i);                         // moving-wall term
                         // g*_i: even (x, ibar), odd (x + c_i, i)
-                        const T fi = PAR == 0 ? back(OPP[i], (uint32_t)n)
-                                              : back(i, nb.at(CX[i], CY[i], CZ[i]));
+                        const T fi = PAR == 0 ? back(OPP[i], gown)
+                                              : back(i, nb.at<true>(CX[i], CY[i], CZ[i]));
                         if (!(SV && svx)) return fi - m;
                         // linear interpolated bounce-back at the wall fraction q
                         // of link i (f_i^in parked above):
@@ -914,13 +1011,13 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
                         const T q = wtab[(int64_t)(i - 1) * wstr + wsl];
                         if (q >= T(0.5)) {
                             // g*_ibar: even (x, i), odd (x - c_i, ibar)
-                            const T fo = PAR == 0 ? back(i, (uint32_t)n)
-                                                  : back(OPP[i], nb.at(-CX[i], -CY[i], -CZ[i]));
+                            const T fo = PAR == 0 ? back(i, gown)
+                                                  : back(OPP[i], nb.at<true>(-CX[i], -CY[i], -CZ[i]));
                             const T r = dev_div(T(1), T(2) * q);
                             return (fi - m) * r + (T(1) - r) * fo;
                         }
-                        const T fin = PAR == 1 ? back(OPP[i], (uint32_t)n)
-                                               : back(i, nb.at(CX[i], CY[i], CZ[i]));
+                        const T fin = PAR == 1 ? back(OPP[i], gown)
+                                               : back(i, nb.at<true>(CX[i], CY[i], CZ[i]));
                         return T(2) * q * fi + (T(1) - T(2) * q) * fin - m;
                     };
                     // a pair (i, ibar) with both ends solid reads the slots the
@@ -931,17 +1028,9 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
                         if (!si && !sj) continue;
                         const T vi = si ? wall_value(i) : T(0);
                         const T vj = sj ? wall_value(j) : T(0);
-                        if (si) Store<SG>::st(gb, j, (uint32_t)n, Store<SG>::scaled ? vi * sg : vi);
-                        if (sj) Store<SG>::st(gb, i, (uint32_t)n, Store<SG>::scaled ? vj * sg : vj);
+                        if (si) Store<SG>::st(gb, j, gown, Store<SG>::scaled ? vi * sg : vi);
+                        if (sj) Store<SG>::st(gb, i, gown, Store<SG>::scaled ? vj * sg : vj);
                     }
-                }
-            } else if (PAR == 1) {
-                // initial populations: f_i(x) also lands in the own slot when
-                // x - c_i is solid
-                for (int i = 1; i < QG; ++i) {
-                    if (!((solid >> OPP[i]) & 1u)) continue;
-                    const T v = g_out<T, MODE>(i, st, rdif);
-                    Store<SG>::st(gb, i, (uint32_t)n, Store<SG>::scaled ? v * sg : v);
                 }
             }
         }
@@ -1053,8 +1142,10 @@ restore_kernel(const Desc* __restrict__ descs, const Tile* __restrict__ tiles,
     Phys<T> ph;
     ph.load(D);
     const int64_t N = uni(D->N);
-    const PopArray<SH, QP> hb = pop_array<SH, QP>(D->h, uni(D->N));
-    const PopArray<SG, QG> gb = pop_array<SG, QG>(D->g, uni(D->N));
+    typedef Lay<SH, SG, QP> LAYT;
+    const auto hb = pop_array<SH, QP, 0, LAYT>(D);
+    const auto gb = pop_array<SG, QG, QP, LAYT>(D);
+    const int nxp = uni(D->nxp);
     const uint8_t* __restrict__ flg = unip(D->flag);
     const uint32_t* __restrict__ lnk = unip(D->link);
     for (int k = 0; k < tl.zn; ++k) {
@@ -1064,12 +1155,12 @@ restore_kernel(const Desc* __restrict__ descs, const Tile* __restrict__ tiles,
         if (flag_kind(f) != KIND_FLUID) continue;
         const uint32_t solid = (f & F_NEAR_WALL) ? (lnk[n] & SOLID_MASK) : 0u;
         Nbr nb;
-        nb.init(x, y, z, nx, ny, nz);
+        nb.init<LAYT>(x, y, z, nx, ny, nz, nxp);
         T dh[QP], dg[QG];
         for (int i = 0; i < QP; ++i) dh[i] = (T)(pops[(int64_t)i * N + n] - wp<QP>(i) * D->href);
         for (int i = 0; i < QG; ++i) dg[i] = (T)(pops[(int64_t)(QP + i) * N + n] - wg(i) * D->gref);
-        place_pops<T, SH, QP, PAR>(hb, (uint32_t)n, nb, solid, ph[PI_SH], dh);
-        place_pops<T, SG, QG, PAR>(gb, (uint32_t)n, nb, solid, ph[PI_SG], dg);
+        place_pops<T, PAR>(hb, nb, solid, ph[PI_SH], dh);
+        place_pops<T, PAR>(gb, nb, solid, ph[PI_SG], dg);
     }
 }
 
@@ -1113,26 +1204,34 @@ ghost_kernel(const Desc* __restrict__ descs, const GhostRef* __restrict__ ghosts
     const T pdb = (T)(Pb * 3.0) - pp[PI_GREF];
     const T iTg = T(3), i2Tg = T(1.5), i2Tg2 = T(4.5);
     const T iTh = T(itp<QP>()), i2Th = T(i2tp<QP>()), i2Th2 = T(i2tp2<QP>());
-    Nbr nb;
-    nb.init(x, y, z, nx, ny, nz);
-    // a launch may mix lattices, so the per-direction bases are per lane here
-    SG* const* gq = (SG* const*)D->gq;
-    SH* const* hq = (SH* const*)D->hq;
+    // a launch may mix lattices, so the population bases are per lane here
+    typedef Lay<SH, SG, QP> LAYT;
+    char* const p0 = (char*)D->pops[0];
+    char* const p1 = (char*)D->pops[1];
+    const int64_t row = (int64_t)(D->nxp >> 6) * LAYT::BLK;
+    // byte address of direction u (h first, then g) of node (xa, ya, za)
+    auto pop_at = [&](int u, int xa, int ya, int za, int size) -> char* {
+        const int64_t off = (int64_t)(xa >> 6) * LAYT::BLK + (int64_t)(xa & 63) * size +
+                            (int64_t)ya * row + (int64_t)za * ny * row +
+                            64 * (LAYT::prefix(u) - (u < LAYT::K ? 0 : LAYT::prefix(LAYT::K)));
+        return (u < LAYT::K ? p0 : p1) + off;
+    };
 #pragma unroll
     for (int i = 1; i < QG; ++i) {
         if (CX[i] * nfx + CY[i] * nfy + CZ[i] * nfz <= 0) continue;
-        const uint32_t y_n = nb.at(CX[i], CY[i], CZ[i]);   // g + c_i
-        if (flag_kind(D->flag[y_n]) != KIND_FLUID) continue;
-        const uint32_t dst = par == 0 ? y_n : (uint32_t)g;
+        // g + c_i (periodic wrap)
+        const int xn = wrapc(x + CX[i], nx), yn = wrapc(y + CY[i], ny), zn = wrapc(z + CZ[i], nz);
+        if (flag_kind(D->flag[xn + (int64_t)nx * (yn + (int64_t)ny * zn)]) != KIND_FLUID) continue;
+        const int xd = par == 0 ? xn : x, yd = par == 0 ? yn : y, zd = par == 0 ? zn : z;
         const int q = par == 0 ? i : OPP[i];
         const T cu = T(CX[i]) * u[0] + T(CY[i]) * u[1] + T(CZ[i]) * u[2];
         const T gam = cu * iTg + cu * cu * i2Tg2 - uu * i2Tg;
         const T vg = T(wg(i)) * (rho * gam + pdb);
-        gq[q][dst] = (SG)(Store<SG>::scaled ? vg * pp[PI_SG] : vg);
+        *(SG*)pop_at(QP + q, xd, yd, zd, (int)sizeof(SG)) = (SG)(Store<SG>::scaled ? vg * pp[PI_SG] : vg);
         if (i < QP) {
             const T gh = cu * iTh + cu * cu * i2Th2 - uu * i2Th;
             const T vh = T(wp<QP>(i)) * ((pc - pp[PI_HREF]) + pc * gh);
-            hq[q][dst] = (SH)(Store<SH>::scaled ? vh * pp[PI_SH] : vh);
+            *(SH*)pop_at(q, xd, yd, zd, (int)sizeof(SH)) = (SH)(Store<SH>::scaled ? vh * pp[PI_SH] : vh);
         }
     }
 }
@@ -1197,17 +1296,17 @@ hipError_t launch_sweep_storage(int qp, int mode, int tx, int parity, Desc* d, c
     return launch_sweep_q<T, SH, SG, QH>(mode, tx, parity, d, tiles, ntiles, diag, ro, in, s);
 }
 
-template <typename T, typename SH>
+template <typename T, typename SH, typename SG>
 hipError_t launch_phi_storage(int qp, int parity, const Desc* d, const Tile* tiles, int ntiles,
                               hipStream_t s, int force) {
     if (ntiles <= 0) return hipSuccess;
     dim3 grid(ntiles), block(NTHREADS);
     const int key = (qp == 19 ? 2 : 0) + (parity & 1);
     switch (key) {
-        case 0: phi_kernel<T, SH, 0, QH><<<grid, block, 0, s>>>(d, tiles, force); break;
-        case 1: phi_kernel<T, SH, 1, QH><<<grid, block, 0, s>>>(d, tiles, force); break;
-        case 2: phi_kernel<T, SH, 0, 19><<<grid, block, 0, s>>>(d, tiles, force); break;
-        default: phi_kernel<T, SH, 1, 19><<<grid, block, 0, s>>>(d, tiles, force); break;
+        case 0: phi_kernel<T, SH, SG, 0, QH><<<grid, block, 0, s>>>(d, tiles, force); break;
+        case 1: phi_kernel<T, SH, SG, 1, QH><<<grid, block, 0, s>>>(d, tiles, force); break;
+        case 2: phi_kernel<T, SH, SG, 0, 19><<<grid, block, 0, s>>>(d, tiles, force); break;
+        default: phi_kernel<T, SH, SG, 1, 19><<<grid, block, 0, s>>>(d, tiles, force); break;
     }
     return hipGetLastError();
 }

@@ -44,6 +44,15 @@ void storage_sizes(int storage, int* sh, int* sg, int* sphi) {
     }
 }
 
+// bytes of one population group (pop_layout): nodes of the row-padded
+// lattice times the group's bytes per node
+int64_t pop_group_bytes(const lbm_params* p) {
+    int sh, sg, sphi;
+    storage_sizes(p->storage, &sh, &sg, &sphi);
+    const PopLayout pl = pop_layout(phase_q(p), sh, sg);
+    return (int64_t)pad_row(p->nx) * p->ny * p->nz * pl.pb;
+}
+
 int validate_params(const lbm_params* p, const lbm_geometry* geo) {
     if (!p) { set_error("params is NULL"); return LBM_E_INVAL; }
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) {
@@ -53,20 +62,18 @@ int validate_params(const lbm_params* p, const lbm_geometry* geo) {
     const int64_t N = (int64_t)p->nx * p->ny * p->nz;
     if (N >= ((int64_t)1 << 31)) { set_error("lattice of %lld nodes exceeds 2^31", (long long)N); return LBM_E_INVAL; }
     if (p->storage < ST_FP64 || p->storage > ST_FP16_ALL) { set_error("unknown storage mode %d", p->storage); return LBM_E_INVAL; }
-    {
-        // every buffer resource spans at most 10 directions and 4 GiB
-        int sh, sg, sphi;
-        storage_sizes(p->storage, &sh, &sg, &sphi);
-        const int64_t big = (int64_t)10 * N * std::max(sh, sg);
-        if (big >= ((int64_t)1 << 32)) {
-            set_error("lattice of %lld nodes: 10 population directions exceed 4 GiB in this storage mode",
-                      (long long)N);
-            return LBM_E_INVAL;
-        }
-    }
     if (p->q_phase != 0 && p->q_phase != 7 && p->q_phase != 19) {
         set_error("q_phase %d: the phase lattice is D3Q7 (7) or D3Q19 (19)", p->q_phase);
         return LBM_E_INVAL;
+    }
+    {
+        // every population group is one buffer resource of at most 4 GiB
+        const int64_t big = pop_group_bytes(p);
+        if (big >= ((int64_t)1 << 32)) {
+            set_error("lattice of %lld nodes (rows padded to %d): a population group of %lld bytes exceeds "
+                      "4 GiB in this storage mode", (long long)N, pad_row(p->nx), (long long)big);
+            return LBM_E_INVAL;
+        }
     }
     if (p->subvoxel != 0 && p->subvoxel != 1) {
         set_error("subvoxel %d: 0 (voxel walls) or 1 (walls from a signed distance)", p->subvoxel);
@@ -183,8 +190,13 @@ static void layout_offsets(const lbm_params* p, int64_t ntiles, int64_t nghosts,
     size_t o = 0;
     L->off_desc = o; o = align256(o + sizeof(Desc));
     L->off_counter = o; o = align256(o + sizeof(unsigned int));
-    L->off_h = o; o = align256(o + (size_t)phase_q(p) * N * sh);
-    L->off_g = o; o = align256(o + (size_t)QG * N * sg);
+    {
+        const PopLayout pl = pop_layout(phase_q(p), sh, sg);
+        L->pop_bytes = (size_t)pop_group_bytes(p);
+        L->off_pop0 = o; o = align256(o + L->pop_bytes);
+        L->off_pop1 = L->off_pop0;
+        if (pl.G == 2) { L->off_pop1 = o; o = align256(o + L->pop_bytes); }
+    }
     L->off_phi = o; o = align256(o + (size_t)N * sphi);
     L->off_flag = o; o = align256(o + (size_t)N);
     L->off_link = o; o = align256(o + (size_t)N * 4);
@@ -379,15 +391,10 @@ void fill_desc(const lbm_params* p, const lbm_geometry* geo, const LatticeLayout
     d->N = L.N;
     d->storage = p->storage;
     d->ntiles = (int)L.tiles.size();
-    d->h = base + L.off_h;
-    d->g = base + L.off_g;
-    {
-        int sh, sg, sphi;
-        storage_sizes(p->storage, &sh, &sg, &sphi);
-        for (int q = 0; q < phase_q(p); ++q) d->hq[q] = base + L.off_h + (size_t)q * L.N * sh;
-        for (int q = phase_q(p); q < QHMAX; ++q) d->hq[q] = nullptr;
-        for (int q = 0; q < QG; ++q) d->gq[q] = base + L.off_g + (size_t)q * L.N * sg;
-    }
+    d->nxp = pad_row(p->nx);
+    d->Np = (int64_t)d->nxp * p->ny * p->nz;
+    d->pops[0] = base + L.off_pop0;
+    d->pops[1] = base + L.off_pop1;
     d->phi = base + L.off_phi;
     d->flag = (const uint8_t*)(base + L.off_flag);
     d->link = (const uint32_t*)(base + L.off_link);
@@ -495,8 +502,8 @@ int upload_and_init(const lbm_params* p, const lbm_geometry* geo, const lbm_init
     int sh, sg, sphi;
     storage_sizes(p->storage, &sh, &sg, &sphi);
     // zero populations and phi (solid slots stay zero), upload geometry
-    HIPCHK(hipMemsetAsync(base + L.off_h, 0, (size_t)phase_q(p) * N * sh, s));
-    HIPCHK(hipMemsetAsync(base + L.off_g, 0, (size_t)QG * N * sg, s));
+    HIPCHK(hipMemsetAsync(base + L.off_pop0, 0, L.pop_bytes, s));
+    if (L.off_pop1 != L.off_pop0) HIPCHK(hipMemsetAsync(base + L.off_pop1, 0, L.pop_bytes, s));
     HIPCHK(hipMemsetAsync(base + L.off_counter, 0, sizeof(unsigned int), s));
     HIPCHK(hipMemsetAsync(base + L.off_partials, 0, L.tiles.size() * NPART * sizeof(double), s));
     HIPCHK(hipMemcpyAsync(base + L.off_flag, L.flag.data(), N, hipMemcpyHostToDevice, s));

@@ -20,7 +20,7 @@ struct LatticeLayout {
     int64_t N = 0;
     int64_t n_fluid = 0, n_ghost = 0, n_solid = 0;
     int64_t n_wall = 0;           // near-wall fluid nodes with a slot (hysteresis, sub-voxel walls)
-    size_t off_desc = 0, off_counter = 0, off_h = 0, off_g = 0, off_phi = 0, off_flag = 0,
+    size_t off_desc = 0, off_counter = 0, off_pop0 = 0, off_pop1 = 0, pop_bytes = 0, off_phi = 0, off_flag = 0,
            off_link = 0, off_tiles = 0, off_partials = 0, off_gbuf = 0, off_ghosts = 0,
            off_wslot = 0, off_hyst = 0, off_wall = 0, total = 0;
     int64_t gface_base[6] = {0, 0, 0, 0, 0, 0};

@@ -1,8 +1,8 @@
 // pflbm.hpp -- device-side data layout of the MI355X phase-field LB library.
 //
 // One lattice lives in HBM as
-//   h   [7][N]  phase-field populations (D3Q7), structure of arrays, x fastest
-//   g   [19][N] hydrodynamic populations (D3Q19)
+//   pops        phase-field populations h (D3Q7) and hydrodynamic populations
+//               g (D3Q19) in blocks of 64 nodes (pop_layout below)
 //   phi [N]     order parameter of the current step (written by the phi pass)
 //   flag[N]     node kind / material / face / near-wall / ghost-owner bits
 //   link[N]     per-node solid-link mask and owned pressure faces
@@ -43,6 +43,35 @@ constexpr int ST_FP64 = 0, ST_FP32 = 1, ST_FP32_SHIFT = 2, ST_FP16_G = 3, ST_FP1
 constexpr uint32_t SOLID_MASK = 0x7FFFEu;  // link bits 1..18
 constexpr int WALL_ROWS = 21;              // sub-voxel wall table: 18 fractions + normal
 
+// ---- population layout: blocked structure of arrays.  Rows are padded to
+// nxp = 64 ceil(nx / 64) nodes; node p = x + nxp (y + ny z) of the padded
+// lattice lies in block p / 64 at lane p % 64.  The directions h_0 .. h_{QP-1},
+// g_0 .. g_18 form G groups of consecutive directions (G = 1 while a node's
+// populations take at most 104 bytes, else 2, cut near half the bytes).  A
+// group is an array of blocks; a block holds the group's directions one after
+// another, 64 lanes each, so the 64 nodes of a wave find all populations of
+// a group in one contiguous span.  Both groups use the larger group's block
+// size, so a node's byte offset within a group is the same in each.  Every
+// group is addressed with 32-bit offsets (at most 4 GiB).
+struct PopLayout {
+    int G;    // groups (1 or 2)
+    int k;    // first direction of group 1 (QP + 19 when G = 1)
+    int pb;   // bytes per node in every group (the block holds 64 pb bytes)
+};
+// bytes per node of the directions before direction u (h first, then g)
+__host__ __device__ constexpr int pop_prefix(int u, int qp, int sh, int sg) {
+    return u <= qp ? u * sh : qp * sh + (u - qp) * sg;
+}
+__host__ __device__ constexpr PopLayout pop_layout(int qp, int sh, int sg) {
+    const int tot = qp * sh + 19 * sg;
+    if (tot <= 104) return PopLayout{1, qp + 19, tot};
+    int k = 1;
+    while (2 * pop_prefix(k, qp, sh, sg) < tot) ++k;
+    const int a = pop_prefix(k, qp, sh, sg);
+    return PopLayout{2, k, a > tot - a ? a : tot - a};
+}
+__host__ __device__ constexpr int pad_row(int nx) { return (nx + 63) / 64 * 64; }
+
 struct alignas(16) Tile {
     int32_t lat;      // lattice index in the descriptor array
     int32_t x0, y0;   // first column of the tile
@@ -59,11 +88,9 @@ struct alignas(256) Desc {
     int32_t storage;
     int32_t ntiles;                // tiles of this lattice
     int32_t q_phase;               // phase lattice: 7 or 19
-    int32_t pad_q;
-    void* h;
-    void* g;
-    void* hq[QHMAX];               // h + q N: base of each phase direction
-    void* gq[19];
+    int32_t nxp;                   // padded row length of the population layout
+    void* pops[2];                 // population groups (pops[1] = pops[0] when G = 1)
+    int64_t Np;                    // nodes of the padded lattice, nxp ny nz
     void* phi;
     const uint8_t* flag;
     const uint32_t* link;
