@@ -514,7 +514,7 @@ __device__ inline void h_eq_pair(int i, const NodeState<T>& s, T href, T& hp, T&
 // SV: instance with the interpolated bounce-back of sub-voxel walls (step
 // mode only; lattices without sub-voxel walls keep half-way walls in it).
 template <typename T, typename SH, typename SG, int MODE, bool DIAG, int TX, int PAR, int QP, bool SV = false>
-__global__ void __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(1)))
+__global__ void __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(PAR == 1 && sizeof(T) == 4 ? 4 : 1)))
 sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut ro, InitIn in) {
     // LDS ring of phi and flags: each plane holds the tile plus a one-node
     // halo, LN cells, staged NST cells per thread
@@ -594,6 +594,12 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
     stage(2, tl.z0 + 1);
     __syncthreads();
     const int c0 = (ty + 1) * LW + (tx + 1);
+    // link word of the node (solid-link mask, owned ghost faces), fetched one
+    // plane ahead from the staged flags: the odd step's population addresses
+    // depend on it
+    constexpr uint8_t LINKED = F_NEAR_WALL | F_OWNER;
+    uint32_t lk_next = 0u;
+    if (active && (s_flag[1][c0] & LINKED)) lk_next = lnk[x + nx * y + nxy * tl.z0];
     for (int k = 0; k < tl.zn; ++k) {
         const int z = tl.z0 + k;
         const bool more = k + 1 < tl.zn;
@@ -606,6 +612,9 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
             for (int j = 0; j < NST; ++j)
                 if (coff[j] >= 0) { nv[j] = phig[coff[j] + zo]; nf[j] = flg[coff[j] + zo]; }
         }
+        const uint32_t links = lk_next;
+        lk_next = 0u;
+        if (more && active && (s_flag[(k + 2) & 3][c0] & LINKED)) lk_next = lnk[x + nx * y + nxy * (z + 1)];
         do {
         if (!active) continue;
         const int sm = k & 3, s0 = (k + 1) & 3, sp = (k + 2) & 3;
@@ -628,7 +637,6 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
             }
             continue;
         }
-        const uint32_t links = (f & (F_NEAR_WALL | F_OWNER)) ? lnk[n] : 0u;
         const uint32_t solid = links & SOLID_MASK;
         Nbr nb;
         nb.init<LAYT>(x, y, z, nx, ny, nz, nxp);
