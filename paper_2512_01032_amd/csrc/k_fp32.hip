@@ -24,4 +24,8 @@ hipError_t launch_ghosts_fp32(int qp, const Desc* d, const GhostRef* ghosts, int
     return launch_ghosts_storage<float, float, float>(qp, d, ghosts, nghosts, s);
 }
 
+hipError_t launch_wall_fp32(int mode, const Desc* d, const WallRef* walls, int nwalls, hipStream_t s) {
+    return launch_wall_compute<float>(mode, d, walls, nwalls, s);
+}
+
 }  // namespace pflbm

@@ -38,6 +38,15 @@ hipError_t launch_sweep_fp16a(int, int, int, int, Desc*, const Tile*, int, int, 
 hipError_t launch_phi_fp16a(int, int, const Desc*, const Tile*, int, hipStream_t, int);
 hipError_t launch_restore_fp16a(int, int, const Desc*, const Tile*, int, const double*, hipStream_t);
 hipError_t launch_ghosts_fp16a(int, const Desc*, const GhostRef*, int, hipStream_t);
+hipError_t launch_wall_fp64(int, const Desc*, const WallRef*, int, hipStream_t);
+hipError_t launch_wall_fp32(int, const Desc*, const WallRef*, int, hipStream_t);
+
+// the wall pass depends only on the compute type
+hipError_t launch_wall(int storage, int mode, const Desc* d, const WallRef* walls, int nwalls,
+                       hipStream_t s) {
+    if (storage == ST_FP64) return launch_wall_fp64(mode, d, walls, nwalls, s);
+    return launch_wall_fp32(mode, d, walls, nwalls, s);
+}
 
 hipError_t launch_sweep(int storage, int qp, int mode, int tx, int parity, Desc* d, const Tile* tiles,
                         int ntiles, int diag, ReadOut ro, InitIn in, hipStream_t s) {

@@ -511,6 +511,141 @@ __device__ inline void h_eq_pair(int i, const NodeState<T>& s, T href, T& hp, T&
     hm = w * (e - o);
 }
 
+// ---------------------------------------------------------------- wall pass
+// Every near-wall fluid node, after the phi pass (Sec. II.B, Eqs. 17-19): the
+// wall normal into the fluid from the solid links (sub-voxel walls: from the
+// table); the neutral pre-gradient (the node's own phi at the solid links);
+// w = -cos(theta) n + sin(theta) t with t the unit tangential part of the
+// pre-gradient; the wetting value phi_s,i from the tanh profile through
+// phi(x) shifted by d_i = w . c_i at each solid link; and the gradient and
+// Laplacian sums with them, in the difference form the sweep uses (Eq. 16).
+// Contact-angle hysteresis (Sec. III.A) blends and records the wall values
+// here.  The sweep takes the sums and the normal of its near-wall nodes from
+// this pass, so its waves do not branch into the wetting arithmetic.
+// Each block's entries belong to one lattice (the launch table pads every
+// lattice's list to a multiple of the block size with node -1), so the
+// lattice's constants are block-uniform scalars; all neighbour loads are
+// issued before the arithmetic.
+template <typename T, int MODE>
+__global__ void __launch_bounds__(NTHREADS)
+wall_kernel(const Desc* __restrict__ descs, const WallRef* __restrict__ walls, int nwalls) {
+    __shared__ T s_cs[2][16];   // cos and sin of each material's contact angle
+    const int k = blockIdx.x * NTHREADS + threadIdx.x;
+    WallRef wr = {0, -1, 0, 0u};
+    if (k < nwalls) wr = walls[k];
+    const int lat = uni(walls[blockIdx.x * NTHREADS].lat);
+    const Desc* D = descs + lat;
+    if (threadIdx.x < 16) {
+        s_cs[0][threadIdx.x] = (T)D->cos_t[threadIdx.x];
+        s_cs[1][threadIdx.x] = (T)D->sin_t[threadIdx.x];
+    }
+    __syncthreads();
+    if (MODE == MODE_STEP && uni(D->step) >= uni(D->stop_step)) return;
+    if (wr.node < 0) return;
+    const int nx = uni(D->nx), ny = uni(D->ny), nz = uni(D->nz);
+    const int n = wr.node;
+    const int64_t sl = wr.slot, nwl = uni(D->n_wall);
+    const int x = n % nx, y = (n / nx) % ny, z = n / (nx * ny);
+    const T* __restrict__ phig = unip((const T*)D->phi);
+    const uint32_t solid = wr.solid;
+    const T* pp = unip(param_block<T>(D));
+    const T iTg = T(3);
+    const int xs[3] = {x == 0 ? nx - 1 : x - 1, x, x == nx - 1 ? 0 : x + 1};
+    const int ys[3] = {y == 0 ? ny - 1 : y - 1, y, y == ny - 1 ? 0 : y + 1};
+    const int zs[3] = {z == 0 ? nz - 1 : z - 1, z, z == nz - 1 ? 0 : z + 1};
+    auto nid = [&](int i) -> int {
+        return xs[CX[i] + 1] + nx * (ys[CY[i] + 1] + ny * zs[CZ[i] + 1]);
+    };
+    // phi of the fluid and ghost neighbours; materials of the solid ones
+    T nv[19];
+#pragma unroll
+    for (int i = 1; i < 19; ++i) nv[i] = ((solid >> i) & 1u) ? T(0) : phig[nid(i)];
+    const uint32_t* __restrict__ wm = unip(D->wmat);
+    const uint32_t mw[3] = {wm[sl], wm[nwl + sl], wm[2 * nwl + sl]};
+    const T pc = phig[n];
+    T gx = T(0), gy = T(0), gz = T(0), lap = T(0);
+    auto pair_sum = [&](int i, T vp, T vm) {
+        const T dv = vp - vm;
+        if (CX[i]) gx += T(wg(i) * CX[i]) * dv;
+        if (CY[i]) gy += T(wg(i) * CY[i]) * dv;
+        if (CZ[i]) gz += T(wg(i) * CZ[i]) * dv;
+        lap += T(wg(i)) * ((vp - pc) + (vm - pc));
+    };
+    T nw[3] = {T(0), T(0), T(0)};
+    if (uni(D->subvoxel)) {
+        const T* __restrict__ wtab = unip((const T*)D->wall);
+        nw[0] = wtab[(QG - 1) * nwl + sl];
+        nw[1] = wtab[QG * nwl + sl];
+        nw[2] = wtab[(QG + 1) * nwl + sl];
+    } else {
+#pragma unroll
+        for (int i = 1; i < 19; ++i) {
+            if (!((solid >> i) & 1u)) continue;
+            nw[0] -= T(wg(i) * CX[i]); nw[1] -= T(wg(i) * CY[i]); nw[2] -= T(wg(i) * CZ[i]);
+        }
+        const T nn = dev_sqrt(nw[0] * nw[0] + nw[1] * nw[1] + nw[2] * nw[2]);
+        const T inn = nn > T(0) ? dev_div(T(1), nn) : T(0);
+        nw[0] *= inn; nw[1] *= inn; nw[2] *= inn;
+    }
+#pragma unroll
+    for (int i = 1; i < 19; i += 2)
+        pair_sum(i, ((solid >> i) & 1u) ? pc : nv[i], ((solid >> (i + 1)) & 1u) ? pc : nv[i + 1]);
+    const T g0[3] = {gx * iTg, gy * iTg, gz * iTg};
+    const T ng = nw[0] * g0[0] + nw[1] * g0[1] + nw[2] * g0[2];
+    T gt[3] = {g0[0] - nw[0] * ng, g0[1] - nw[1] * ng, g0[2] - nw[2] * ng};
+    const T tnn = dev_sqrt(gt[0] * gt[0] + gt[1] * gt[1] + gt[2] * gt[2]);
+    const T itn = dev_div(T(1), tnn + pp[PI_EPS]);
+    gt[0] *= itn; gt[1] *= itn; gt[2] *= itn;
+    T a = T(2) * pc - T(1);
+    a = a > T(1) - pp[PI_CLAMP_A] ? T(1) - pp[PI_CLAMP_A] : a;
+    a = a < -T(1) + pp[PI_CLAMP_A] ? -T(1) + pp[PI_CLAMP_A] : a;
+    const T k2W = pp[PI_K2W];
+    // contact-angle hysteresis (Sec. III.A): the wall value of link i is
+    // blended with one kept from the previous step (history [18][n_wall]):
+    // the blended value that step used (mode 1) or its unblended value
+    // (mode 2); initialisation and a reset pass record the current values
+    const int hmode = uni(D->hysteresis);
+    T* __restrict__ hist = hmode ? unip((T*)D->hyst) : nullptr;
+    const bool record = MODE == MODE_INIT || (MODE == MODE_READ && uni(D->hyst_reset) != 0);
+    auto phis = [&](int i) -> T {
+        const int mat = (mw[(i - 1) / 6] >> (4 * ((i - 1) % 6))) & 15u;
+        const T ct = s_cs[0][mat], sn = s_cs[1][mat];
+        const T d = -ct * cdot(i, nw[0], nw[1], nw[2]) + sn * cdot(i, gt[0], gt[1], gt[2]);
+        // tanh(artanh(a) + 2d/W) by the addition theorem: phi_s,i is exactly
+        // phi(x) where d_i = 0 (a link along the normal of a 90-degree wall),
+        // so the Laplacian there is exactly zero as in the FP64 model and the
+        // sign term of the mobility correction does not flip on rounding noise
+        const T t = dev_tanh(k2W * d);
+        T ps = T(0.5) * (T(1) + dev_div(a + t, T(1) + a * t));
+        if (hmode) {
+            T* hp = hist + (int64_t)(i - 1) * nwl + sl;
+            if (record) {
+                *hp = ps;
+            } else {
+                const T fresh = ps;
+                ps = pp[PI_HBETA] * *hp + pp[PI_HBETA1] * fresh;
+                if (MODE == MODE_STEP) *hp = hmode == 2 ? fresh : ps;
+            }
+        }
+        return ps;
+    };
+    gx = gy = gz = lap = T(0);
+#pragma unroll
+    for (int i = 1; i < 19; i += 2) {
+        const T vp = ((solid >> i) & 1u) ? phis(i) : nv[i];
+        const T vm = ((solid >> (i + 1)) & 1u) ? phis(i + 1) : nv[i + 1];
+        pair_sum(i, vp, vm);
+    }
+    T* __restrict__ out = unip((T*)D->wgl);
+    out[sl] = gx;
+    out[nwl + sl] = gy;
+    out[2 * nwl + sl] = gz;
+    out[3 * nwl + sl] = lap;
+    out[4 * nwl + sl] = nw[0];
+    out[5 * nwl + sl] = nw[1];
+    out[6 * nwl + sl] = nw[2];
+}
+
 // SV: instance with the interpolated bounce-back of sub-voxel walls (step
 // mode only; lattices without sub-voxel walls keep half-way walls in it).
 template <typename T, typename SH, typename SG, int MODE, bool DIAG, int TX, int PAR, int QP, bool SV = false>
@@ -524,7 +659,6 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
     __shared__ uint8_t s_flag[4][LN];
     __shared__ double s_red[NPART][NTHREADS / 64];
     __shared__ int s_last;
-    __shared__ T s_cs[2][16];   // cos and sin of each wall material's contact angle
 
     const Tile tl = load_tile(tiles);
     Desc* D = descs + tl.lat;
@@ -585,10 +719,6 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
     // slot of plane z-2 (last read in the previous iteration) after it, so
     // their latency overlaps the population traffic, and one barrier per
     // plane orders the ring.
-    if (tid < 16) {
-        s_cs[0][tid] = (T)D->cos_t[tid];
-        s_cs[1][tid] = (T)D->sin_t[tid];
-    }
     stage(0, tl.z0 - 1);
     stage(1, tl.z0);
     stage(2, tl.z0 + 1);
@@ -598,8 +728,11 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
     // plane ahead from the staged flags: the odd step's population addresses
     // depend on it
     constexpr uint8_t LINKED = F_NEAR_WALL | F_OWNER;
+    const int32_t* __restrict__ wsl_arr = unip(D->wslot);
     uint32_t lk_next = 0u;
+    int32_t ws_next = 0;
     if (active && (s_flag[1][c0] & LINKED)) lk_next = lnk[x + nx * y + nxy * tl.z0];
+    if (active && (s_flag[1][c0] & F_NEAR_WALL)) ws_next = wsl_arr[x + nx * y + nxy * tl.z0];
     for (int k = 0; k < tl.zn; ++k) {
         const int z = tl.z0 + k;
         const bool more = k + 1 < tl.zn;
@@ -613,8 +746,14 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
                 if (coff[j] >= 0) { nv[j] = phig[coff[j] + zo]; nf[j] = flg[coff[j] + zo]; }
         }
         const uint32_t links = lk_next;
+        const int32_t wslot_cur = ws_next;
         lk_next = 0u;
-        if (more && active && (s_flag[(k + 2) & 3][c0] & LINKED)) lk_next = lnk[x + nx * y + nxy * (z + 1)];
+        ws_next = 0;
+        if (more && active) {
+            const uint8_t fn = s_flag[(k + 2) & 3][c0];
+            if (fn & LINKED) lk_next = lnk[x + nx * y + nxy * (z + 1)];
+            if (fn & F_NEAR_WALL) ws_next = wsl_arr[x + nx * y + nxy * (z + 1)];
+        }
         do {
         if (!active) continue;
         const int sm = k & 3, s0 = (k + 1) & 3, sp = (k + 2) & 3;
@@ -668,93 +807,19 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
         // sub-voxel walls: per-slot table of link fractions and wall normal
         const bool svx = uni(D->subvoxel) != 0;
         const T* __restrict__ wtab = nullptr;
-        int64_t wsl = 0, wstr = 0;
-        if (solid && svx) {
-            wtab = unip((const T*)D->wall);
-            wstr = uni(D->n_wall);
-            wsl = D->wslot[n];
-        }
+        const int64_t wsl = wslot_cur, wstr = uni(D->n_wall);
+        if (solid && svx) wtab = unip((const T*)D->wall);
         if (solid) {
-            // wetting (Eqs. 17-19).  Wall normal into the fluid from the solid
-            // links (sub-voxel walls: from the table); neutral pre-gradient
-            // (the node's own phi at the solid links); w = -cos(theta) n +
-            // sin(theta) t with t the unit tangential part of the pre-gradient;
-            // phi_s,i from the tanh profile through phi(x) shifted by
-            // d_i = w . c_i; the stencil is evaluated again with phi_s,i at the
-            // solid links
-            if (svx) {
-                nw[0] = wtab[(QG - 1) * wstr + wsl];
-                nw[1] = wtab[QG * wstr + wsl];
-                nw[2] = wtab[(QG + 1) * wstr + wsl];
-            } else {
-                for (int i = 1; i < 19; ++i) {
-                    if (!((solid >> i) & 1u)) continue;
-                    nw[0] -= T(wg(i) * CX[i]); nw[1] -= T(wg(i) * CY[i]); nw[2] -= T(wg(i) * CZ[i]);
-                }
-                const T nn = dev_sqrt(nw[0] * nw[0] + nw[1] * nw[1] + nw[2] * nw[2]);
-                const T inn = nn > T(0) ? dev_div(T(1), nn) : T(0);
-                nw[0] *= inn; nw[1] *= inn; nw[2] *= inn;
-            }
-            gx = gy = gz = lap = T(0);
-#pragma unroll
-            for (int i = 1; i < 19; i += 2)
-                pair_sum(i, ((solid >> i) & 1u) ? pc : nbv(i), ((solid >> (i + 1)) & 1u) ? pc : nbv(i + 1));
-            const T g0[3] = {gx * iTg, gy * iTg, gz * iTg};
-            const T ng = nw[0] * g0[0] + nw[1] * g0[1] + nw[2] * g0[2];
-            T gt[3] = {g0[0] - nw[0] * ng, g0[1] - nw[1] * ng, g0[2] - nw[2] * ng};
-            const T tnn = dev_sqrt(gt[0] * gt[0] + gt[1] * gt[1] + gt[2] * gt[2]);
-            const T itn = dev_div(T(1), tnn + ph[PI_EPS]);
-            gt[0] *= itn; gt[1] *= itn; gt[2] *= itn;
-            T a = T(2) * pc - T(1);
-            a = a > T(1) - ph[PI_CLAMP_A] ? T(1) - ph[PI_CLAMP_A] : a;
-            a = a < -T(1) + ph[PI_CLAMP_A] ? -T(1) + ph[PI_CLAMP_A] : a;
-            const T k2W = ph[PI_K2W];
-            // contact-angle hysteresis (Sec. III.A): the wall value of link i
-            // is blended with one kept from the previous step (history slot
-            // wslot[n], [18][n_wall] layout): the blended value that step used
-            // (mode 1) or its unblended value (mode 2); initialisation and a
-            // reset pass record the current values
-            const int hmode = uni(D->hysteresis);
-            const bool hyst = hmode != 0;
-            T* __restrict__ hist = nullptr;
-            int64_t hslot = 0, hstride = 0;
-            if (hyst) {
-                hist = unip((T*)D->hyst);
-                hstride = uni(D->n_wall);
-                hslot = D->wslot[n];
-            }
-            const bool record = MODE == MODE_INIT || (MODE == MODE_READ && uni(D->hyst_reset) != 0);
-            auto phis = [&](int i) -> T {
-                const int cx = CX[i], cy = CY[i], cz = CZ[i];
-                const int sl = cz < 0 ? sm : (cz > 0 ? sp : s0);
-                const int mat = flag_sub(s_flag[sl][c0 + cy * LW + cx]);
-                const T ct = s_cs[0][mat], sn = s_cs[1][mat];
-                const T d = -ct * cdot(i, nw[0], nw[1], nw[2]) + sn * cdot(i, gt[0], gt[1], gt[2]);
-                // tanh(artanh(a) + 2d/W) by the addition theorem: phi_s,i is
-                // exactly phi(x) where d_i = 0 (a link along the normal of a
-                // 90-degree wall), so the Laplacian there is exactly zero as
-                // in the FP64 model and the sign term of the mobility
-                // correction does not flip on rounding noise
-                const T t = dev_tanh(k2W * d);
-                T ps = T(0.5) * (T(1) + dev_div(a + t, T(1) + a * t));
-                if (hyst) {
-                    T* hp = hist + (int64_t)(i - 1) * hstride + hslot;
-                    if (record) {
-                        *hp = ps;
-                    } else {
-                        const T fresh = ps;
-                        ps = ph[PI_HBETA] * *hp + ph[PI_HBETA1] * fresh;
-                        if (MODE == MODE_STEP) *hp = hmode == 2 ? fresh : ps;
-                    }
-                }
-                return ps;
-            };
-            gx = gy = gz = lap = T(0);
-            for (int i = 1; i < 19; i += 2) {
-                const T vp = ((solid >> i) & 1u) ? phis(i) : nbv(i);
-                const T vm = ((solid >> (i + 1)) & 1u) ? phis(i + 1) : nbv(i + 1);
-                pair_sum(i, vp, vm);
-            }
+            // wetting (Eqs. 17-19): the stencil sums with the wall values and
+            // the wall normal come from the wall pass
+            const T* __restrict__ wgl = unip((const T*)D->wgl);
+            gx = wgl[wsl];
+            gy = wgl[wstr + wsl];
+            gz = wgl[2 * wstr + wsl];
+            lap = wgl[3 * wstr + wsl];
+            nw[0] = wgl[4 * wstr + wsl];
+            nw[1] = wgl[5 * wstr + wsl];
+            nw[2] = wgl[6 * wstr + wsl];
         }
         st.grad[0] = gx * iTg; st.grad[1] = gy * iTg; st.grad[2] = gz * iTg;
         lap = T(6) * lap;
@@ -1246,6 +1311,19 @@ ghost_kernel(const Desc* __restrict__ descs, const GhostRef* __restrict__ ghosts
 
 
 // -------------------------------------------------------------- launchers
+template <typename T>
+hipError_t launch_wall_compute(int mode, const Desc* d, const WallRef* walls, int nwalls, hipStream_t s) {
+    if (nwalls <= 0) return hipSuccess;
+    dim3 grid((nwalls + NTHREADS - 1) / NTHREADS), block(NTHREADS);
+    switch (mode) {
+        case MODE_STEP: wall_kernel<T, MODE_STEP><<<grid, block, 0, s>>>(d, walls, nwalls); break;
+        case MODE_READ: wall_kernel<T, MODE_READ><<<grid, block, 0, s>>>(d, walls, nwalls); break;
+        case MODE_INIT: wall_kernel<T, MODE_INIT><<<grid, block, 0, s>>>(d, walls, nwalls); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <typename T, typename SH, typename SG>
 hipError_t launch_ghosts_storage(int qp, const Desc* d, const GhostRef* ghosts, int nghosts,
                                  hipStream_t s) {

@@ -207,8 +207,10 @@ static void layout_offsets(const lbm_params* p, int64_t ntiles, int64_t nghosts,
     // per-node slot of near-wall fluid nodes (hysteresis, sub-voxel walls);
     // hysteresis: 18 wall values per slot; sub-voxel walls: 18 link
     // fractions and the wall normal per slot
-    const bool slots = p->hysteresis || p->subvoxel;
-    L->off_wslot = o; if (slots) o = align256(o + (size_t)N * 4);
+    L->off_wslot = o; o = align256(o + (size_t)N * 4);
+    L->off_wgl = o; o = align256(o + (size_t)WG_ROWS * L->n_wall * sphi);
+    L->off_wrefs = o; o = align256(o + (size_t)L->n_wall * sizeof(WallRef));
+    L->off_wmat = o; o = align256(o + (size_t)3 * L->n_wall * 4);
     L->off_hyst = o; if (p->hysteresis) o = align256(o + (size_t)(QG - 1) * L->n_wall * sphi);
     L->off_wall = o; if (p->subvoxel) o = align256(o + (size_t)WALL_ROWS * L->n_wall * sphi);
     L->total = o;
@@ -305,13 +307,23 @@ int build_layout(const lbm_params* p, const lbm_geometry* geo, int lat, LatticeL
     // slots of the near-wall fluid nodes, in node order (coalesced along x)
     L->n_wall = 0;
     std::vector<double>().swap(L->wall);
-    if (p->hysteresis || p->subvoxel) {
-        L->wslot.assign(N, -1);
-        for (int64_t n = 0; n < N; ++n)
-            if ((L->link[n] & SOLID_MASK) && flag_kind(L->flag[n]) == KIND_FLUID)
-                L->wslot[n] = (int32_t)L->n_wall++;
-    } else {
-        std::vector<int32_t>().swap(L->wslot);
+    L->wslot.assign(N, -1);
+    L->walls.clear();
+    for (int64_t n = 0; n < N; ++n)
+        if ((L->link[n] & SOLID_MASK) && flag_kind(L->flag[n]) == KIND_FLUID) {
+            L->walls.push_back(WallRef{0, (int32_t)n, (int32_t)L->n_wall, L->link[n] & SOLID_MASK});
+            L->wslot[n] = (int32_t)L->n_wall++;
+        }
+    // materials of the solid links, packed per slot
+    L->wmat.assign((size_t)3 * L->n_wall, 0u);
+    for (const WallRef& w : L->walls) {
+        const int64_t n = w.node;
+        const int x = (int)(n % nx), y = (int)((n / nx) % ny), z = (int)(n / ((int64_t)nx * ny));
+        for (int i = 1; i < 19; ++i) {
+            if (!((L->link[n] >> i) & 1u)) continue;
+            const int64_t m = (x + HCX[i] + nx) % nx + (int64_t)nx * ((y + HCY[i] + ny) % ny + (int64_t)ny * ((z + HCZ[i] + nz) % nz));
+            L->wmat[(size_t)((i - 1) / 6) * L->n_wall + w.slot] |= (uint32_t)flag_sub(L->flag[m]) << (4 * ((i - 1) % 6));
+        }
     }
     if (p->subvoxel) {
         // sub-voxel walls from the signed distance (> 0 in the fluid): the
@@ -403,9 +415,10 @@ void fill_desc(const lbm_params* p, const lbm_geometry* geo, const LatticeLayout
     d->q_phase = phase_q(p);
     d->hysteresis = p->hysteresis;
     d->hyst_reset = 0;
-    const bool slots = p->hysteresis || p->subvoxel;
-    d->n_wall = slots ? L.n_wall : 0;
-    d->wslot = slots ? (const int32_t*)(base + L.off_wslot) : nullptr;
+    d->n_wall = L.n_wall;
+    d->wslot = (const int32_t*)(base + L.off_wslot);
+    d->wgl = base + L.off_wgl;
+    d->wmat = (const uint32_t*)(base + L.off_wmat);
     d->hyst = p->hysteresis ? (void*)(base + L.off_hyst) : nullptr;
     d->subvoxel = p->subvoxel ? 1 : 0;
     d->wall = p->subvoxel ? (void*)(base + L.off_wall) : nullptr;
@@ -508,8 +521,12 @@ int upload_and_init(const lbm_params* p, const lbm_geometry* geo, const lbm_init
     HIPCHK(hipMemsetAsync(base + L.off_partials, 0, L.tiles.size() * NPART * sizeof(double), s));
     HIPCHK(hipMemcpyAsync(base + L.off_flag, L.flag.data(), N, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(base + L.off_link, L.link.data(), (size_t)N * 4, hipMemcpyHostToDevice, s));
-    if (p->hysteresis || p->subvoxel)
-        HIPCHK(hipMemcpyAsync(base + L.off_wslot, L.wslot.data(), (size_t)N * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(base + L.off_wslot, L.wslot.data(), (size_t)N * 4, hipMemcpyHostToDevice, s));
+    if (L.n_wall) {
+        HIPCHK(hipMemcpyAsync(base + L.off_wrefs, L.walls.data(), L.walls.size() * sizeof(WallRef),
+                              hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(base + L.off_wmat, L.wmat.data(), L.wmat.size() * 4, hipMemcpyHostToDevice, s));
+    }
     if (p->subvoxel && L.n_wall) {
         // wall table in the compute type (a synchronous copy: the host
         // buffer is temporary)
@@ -554,7 +571,8 @@ int upload_and_init(const lbm_params* p, const lbm_geometry* geo, const lbm_init
             const int32_t on = 1, off = 0;
             HIPCHK(hipMemcpyAsync(&ddesc->hyst_reset, &on, sizeof(on), hipMemcpyHostToDevice, s));
             HIPCHK(hipStreamSynchronize(s));
-            int rc = read_lattice(p->storage, *hdesc, (int)(step0 & 1), ddesc, dtiles, nt, 0, nullptr,
+            int rc = read_lattice(p->storage, *hdesc, (int)(step0 & 1), ddesc, dtiles, nt,
+                                  (const WallRef*)(base + L.off_wrefs), (int)L.n_wall, 0, nullptr,
                                   nullptr, nullptr, nullptr, s);
             HIPCHK(hipMemcpyAsync(&ddesc->hyst_reset, &off, sizeof(off), hipMemcpyHostToDevice, s));
             HIPCHK(hipStreamSynchronize(s));
@@ -593,7 +611,9 @@ int upload_and_init(const lbm_params* p, const lbm_geometry* geo, const lbm_init
     }
     ReadOut ro = {nullptr, nullptr, nullptr, nullptr};
     InitIn in = {du, dP};
-    hipError_t e = launch_sweep(p->storage, phase_q(p), MODE_INIT, L.tx, 0, ddesc, dtiles, nt, 0, ro, in, s);
+    hipError_t e = launch_wall(p->storage, MODE_INIT, ddesc, (const WallRef*)(base + L.off_wrefs),
+                               (int)L.n_wall, s);
+    if (e == hipSuccess) e = launch_sweep(p->storage, phase_q(p), MODE_INIT, L.tx, 0, ddesc, dtiles, nt, 0, ro, in, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (du) hipFree(du);
     if (dP) hipFree(dP);
@@ -602,8 +622,8 @@ int upload_and_init(const lbm_params* p, const lbm_geometry* geo, const lbm_init
 }
 
 int read_lattice(int storage, const Desc& hdesc, int parity, Desc* d_desc, const Tile* d_tiles,
-                 int ntiles, uint32_t mask, double* phi, double* P, double* u, double* pops,
-                 hipStream_t s) {
+                 int ntiles, const WallRef* d_walls, int nwalls, uint32_t mask, double* phi,
+                 double* P, double* u, double* pops, hipStream_t s) {
     const int64_t N = hdesc.N;
     const bool want_pop = (mask & (LBM_POP_H | LBM_POP_G)) && pops;
     double* buf = nullptr;
@@ -621,6 +641,7 @@ int read_lattice(int storage, const Desc& hdesc, int parity, Desc* d_desc, const
     ro.pops = want_pop ? buf + o_pop : nullptr;
     InitIn in = {nullptr, nullptr};
     hipError_t e = launch_phi(storage, qh, parity, d_desc, d_tiles, ntiles, s, 1);
+    if (e == hipSuccess) e = launch_wall(storage, MODE_READ, d_desc, d_walls, nwalls, s);
     if (e == hipSuccess) e = launch_sweep(storage, qh, MODE_READ, hdesc.tx, parity, d_desc, d_tiles, ntiles, 1, ro, in, s);
     if (e == hipSuccess && ro.phi) e = hipMemcpyAsync(phi, ro.phi, N * sizeof(double), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess && ro.P) e = hipMemcpyAsync(P, ro.P, N * sizeof(double), hipMemcpyDeviceToHost, s);

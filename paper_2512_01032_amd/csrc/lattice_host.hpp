@@ -19,10 +19,11 @@ struct LatticeLayout {
     int tx = 64, ty = 4, tz = 16;
     int64_t N = 0;
     int64_t n_fluid = 0, n_ghost = 0, n_solid = 0;
-    int64_t n_wall = 0;           // near-wall fluid nodes with a slot (hysteresis, sub-voxel walls)
+    int64_t n_wall = 0;           // near-wall fluid nodes (each has a slot)
     size_t off_desc = 0, off_counter = 0, off_pop0 = 0, off_pop1 = 0, pop_bytes = 0, off_phi = 0, off_flag = 0,
            off_link = 0, off_tiles = 0, off_partials = 0, off_gbuf = 0, off_ghosts = 0,
-           off_wslot = 0, off_hyst = 0, off_wall = 0, total = 0;
+           off_wslot = 0, off_hyst = 0, off_wall = 0, off_wgl = 0, off_wrefs = 0, off_wmat = 0,
+           total = 0;
     int64_t gface_base[6] = {0, 0, 0, 0, 0, 0};
     int64_t gface_count = 0;      // face-buffer entries (per velocity component)
     std::vector<uint8_t> flag;
@@ -31,6 +32,9 @@ struct LatticeLayout {
     std::vector<double> wall;     // sub-voxel walls: [WALL_ROWS][n_wall] link fractions, normal
     std::vector<Tile> tiles;
     std::vector<GhostRef> ghosts;
+    std::vector<WallRef> walls;   // near-wall fluid nodes in slot order (lattice 0)
+    std::vector<uint32_t> wmat;   // [3][n_wall]: material of the solid neighbour of link
+                                  // i in bits 4 ((i - 1) % 6) of word (i - 1) / 6
 };
 
 // Validate parameters (and geometry when given).  Returns LBM_OK or sets the
@@ -68,7 +72,7 @@ int upload_and_init(const lbm_params* p, const lbm_geometry* geo, const lbm_init
 // d_tiles (device).  Synchronous.
 // parity: AA parity of the lattice's current step.
 int read_lattice(int storage, const Desc& hdesc, int parity, Desc* d_desc, const Tile* d_tiles,
-                 int ntiles, uint32_t mask, double* phi, double* P, double* u, double* pops,
-                 hipStream_t s);
+                 int ntiles, const WallRef* d_walls, int nwalls, uint32_t mask, double* phi,
+                 double* P, double* u, double* pops, hipStream_t s);
 
 }  // namespace pflbm

@@ -26,6 +26,8 @@ struct lbm_handle {
     int ntiles = 0;
     GhostRef* dghosts = nullptr;
     int nghosts = 0;
+    WallRef* dwalls = nullptr;   // near-wall fluid nodes (wall pass)
+    int nwalls = 0;
     int64_t step = 0;            // steps queued so far
     // stability flag copied back asynchronously after each lbm_step
     int* h_unstable = nullptr;   // pinned
@@ -111,6 +113,8 @@ extern "C" int lbm_create(const lbm_params* p, const lbm_geometry* geo, const lb
     h->ntiles = (int)h->L.tiles.size();
     h->dghosts = (GhostRef*)(h->base + h->L.off_ghosts);
     h->nghosts = (int)h->L.ghosts.size();
+    h->dwalls = (WallRef*)(h->base + h->L.off_wrefs);
+    h->nwalls = (int)h->L.n_wall;
     h->step = h->hdesc.step;
     // the host copies of flags and links are no longer needed
     std::vector<uint8_t>().swap(h->L.flag);
@@ -170,6 +174,7 @@ extern "C" int lbm_step(lbm_handle* h, int64_t nsteps) {
         }
         const int par = (int)(t & 1);
         HIPRET(launch_phi(storage, qp, par, h->ddesc, h->dtiles, h->ntiles, h->stream));
+        if (h->nwalls) HIPRET(launch_wall(storage, MODE_STEP, h->ddesc, h->dwalls, h->nwalls, h->stream));
         if (h->timing) HIPRET(hipEventRecord(e1, h->stream));
         HIPRET(launch_sweep(storage, qp, h->p.subvoxel ? MODE_STEP_SV : MODE_STEP, h->L.tx, par, h->ddesc, h->dtiles, h->ntiles, diag, ro, in,
                             h->stream));
@@ -203,14 +208,14 @@ extern "C" int lbm_read_fields(lbm_handle* h, uint32_t mask, double* phi, double
     HIPRET(hipSetDevice(h->device));
     HIPRET(hipStreamSynchronize(h->stream));
     return read_lattice(h->p.storage, h->hdesc, (int)(h->step & 1), h->ddesc, h->dtiles, h->ntiles,
-                        mask, phi, P, u, pops, h->stream);
+                        h->dwalls, h->nwalls, mask, phi, P, u, pops, h->stream);
 }
 
 extern "C" int lbm_reduce(lbm_handle* h, lbm_diag* d) {
     if (!h || !d) { set_error("NULL argument"); return LBM_E_INVAL; }
     HIPRET(hipSetDevice(h->device));
     int rc = read_lattice(h->p.storage, h->hdesc, (int)(h->step & 1), h->ddesc, h->dtiles,
-                          h->ntiles, 0, nullptr, nullptr, nullptr, nullptr, h->stream);
+                          h->ntiles, h->dwalls, h->nwalls, 0, nullptr, nullptr, nullptr, nullptr, h->stream);
     if (rc != LBM_OK) return rc;
     double v[NPART];
     HIPRET(hipMemcpy(v, h->ddesc->diag, sizeof(v), hipMemcpyDeviceToHost));

@@ -42,6 +42,8 @@ constexpr int ST_FP64 = 0, ST_FP32 = 1, ST_FP32_SHIFT = 2, ST_FP16_G = 3, ST_FP1
 
 constexpr uint32_t SOLID_MASK = 0x7FFFEu;  // link bits 1..18
 constexpr int WALL_ROWS = 21;              // sub-voxel wall table: 18 fractions + normal
+constexpr int WG_ROWS = 7;                 // wall pass output: gradient and Laplacian
+                                           // sums (4), unit wall normal (3)
 
 // ---- population layout: blocked structure of arrays.  Rows are padded to
 // nxp = 64 ceil(nx / 64) nodes; node p = x + nxp (y + ny z) of the padded
@@ -100,8 +102,12 @@ struct alignas(256) Desc {
     int64_t gface_base[6];         // first entry of each face plane in gbuf
     int64_t gface_count;           // entries per velocity component
     void* hyst;                    // [18][n_wall] wall values of the last step (compute type)
-    const int32_t* wslot;          // [N] slot of a near-wall fluid node in hyst and wall
-    int64_t n_wall;                // near-wall fluid nodes (hysteresis only, else 0)
+    const int32_t* wslot;          // [N] slot of a near-wall fluid node (-1: none)
+    int64_t n_wall;                // near-wall fluid nodes
+    void* wgl;                     // [WG_ROWS][n_wall] (compute type): the wall pass's
+                                   // stencil sums with the wetting values and wall normal
+    const uint32_t* wmat;          // [3][n_wall]: material of the solid neighbour of link i
+                                   // in bits 4 ((i - 1) % 6) of word (i - 1) / 6
     int32_t hysteresis;            // 1, 2: wall values blended with their history (two readings)
     int32_t hyst_reset;            // a read pass records the current wall values instead
     void* wall;                    // sub-voxel walls: [WALL_ROWS][n_wall] (compute type):
@@ -162,6 +168,13 @@ struct GhostRef {              // one pressure ghost: lattice and node
     int32_t node;
 };
 
+struct WallRef {               // one near-wall fluid node
+    int32_t lat;               // lattice
+    int32_t node;              // node index (-1: padding, skipped)
+    int32_t slot;              // slot in the per-lattice wall arrays
+    uint32_t solid;            // solid-link mask (bits 1..18)
+};
+
 // entry of a ghost node (x, y, z) on face f in the face buffer
 __host__ __device__ inline int64_t ghost_slot(const int64_t* base, int f, int x, int y, int z,
                                               int nx, int ny) {
@@ -199,5 +212,10 @@ hipError_t launch_advance(Desc* d, int nlat, hipStream_t s);
 // listed pressure ghost for the next step, from its owner's phi and u
 hipError_t launch_ghosts(int storage, int qp, const Desc* d, const GhostRef* ghosts, int nghosts,
                          hipStream_t s);
+// after the phi pass, before the sweep (mode MODE_STEP, MODE_READ or
+// MODE_INIT of the sweep that follows): wetting values, stencil sums and wall
+// normal of every listed near-wall fluid node
+hipError_t launch_wall(int storage, int mode, const Desc* d, const WallRef* walls, int nwalls,
+                       hipStream_t s);
 
 }  // namespace pflbm

@@ -120,6 +120,9 @@ struct lbm_server {
     size_t tiles_cap = 0;
     GhostRef* dghosts = nullptr;
     size_t ghosts_cap = 0;
+    WallRef* dwalls = nullptr;         // near-wall fluid nodes of every resident lattice
+    size_t walls_cap = 0;
+    int nwalls = 0;
     struct Group { int qp, tx, off, n, sv = 0; };   // sv: lattices with sub-voxel walls
     std::vector<Group> groups;         // sweep launches: one per (phase lattice, tile width)
     std::vector<Group> phi_groups;     // phi launches: one per phase lattice (tx unused)
@@ -234,6 +237,7 @@ int admit_one(lbm_server* s) {
     std::vector<double>().swap(job->L.wall);
     std::vector<uint8_t>().swap(job->L.flag);
     std::vector<uint32_t>().swap(job->L.link);
+    std::vector<int32_t>().swap(job->L.wslot);
     job->geo.solid = nullptr;
     job->geo.sdf = nullptr;
     job->t_admit = s->now();
@@ -278,7 +282,24 @@ int rebuild_tables(lbm_server* s) {
         if ((int)ghosts.size() > goff)
             s->ghost_groups.push_back({qp, 0, goff, (int)ghosts.size() - goff});
     }
+    std::vector<WallRef> walls;
+    for (auto& j : s->active) {
+        for (WallRef w : j->L.walls) { w.lat = j->slot; walls.push_back(w); }
+        // the wall pass takes its lattice constants per block: pad each
+        // lattice's list to whole blocks (node -1 is skipped)
+        while (walls.size() % NTHREADS) walls.push_back(WallRef{j->slot, -1, 0, 0u});
+    }
     for (auto& j : s->active) s->table_slots = std::max(s->table_slots, j->slot + 1);
+    if (walls.size() > s->walls_cap) {
+        if (s->dwalls) SRV_CHK(hipFree(s->dwalls));
+        s->dwalls = nullptr;
+        s->walls_cap = std::max(walls.size(), 2 * s->walls_cap);
+        SRV_CHK(hipMalloc(&s->dwalls, s->walls_cap * sizeof(WallRef)));
+    }
+    if (!walls.empty())
+        SRV_CHK(hipMemcpyAsync(s->dwalls, walls.data(), walls.size() * sizeof(WallRef),
+                               hipMemcpyHostToDevice, s->stream));
+    s->nwalls = (int)walls.size();
     if (tiles.size() > s->tiles_cap) {
         if (s->dtiles) SRV_CHK(hipFree(s->dtiles));
         s->dtiles = nullptr;
@@ -316,6 +337,8 @@ hipError_t enqueue_steps(lbm_server* s) {
         for (const auto& g : s->phi_groups)
             if (e == hipSuccess)
                 e = launch_phi(storage, g.qp, par, s->dtable, s->dtiles + g.off, g.n, s->stream, 0);
+        if (e == hipSuccess && s->nwalls)
+            e = launch_wall(storage, MODE_STEP, s->dtable, s->dwalls, s->nwalls, s->stream);
         for (const auto& g : s->groups)
             if (e == hipSuccess)
                 e = launch_sweep(storage, g.qp, g.sv ? MODE_STEP_SV : MODE_STEP, g.tx, par, s->dtable, s->dtiles + g.off, g.n,
@@ -364,9 +387,10 @@ int finalize(lbm_server* s, std::unique_ptr<Job> job) {
     } else {
         Desc* dd = s->dtable + job->slot;
         const Tile* dt = (const Tile*)(s->arena + job->off + job->L.off_tiles);
+        const WallRef* dw = (const WallRef*)(s->arena + job->off + job->L.off_wrefs);
         int rc = read_lattice(s->cfg.storage, job->hdesc, (int)(job->nsteps & 1), dd, dt,
-                              (int)job->L.tiles.size(), LBM_PHI | LBM_P | LBM_U, job->phi, job->P,
-                              job->u, nullptr, s->stream);
+                              (int)job->L.tiles.size(), dw, (int)job->L.n_wall, LBM_PHI | LBM_P | LBM_U,
+                              job->phi, job->P, job->u, nullptr, s->stream);
         double v[NPART];
         if (rc == LBM_OK) {
             const hipError_t e = hipMemcpy(v, dd->diag, sizeof(v), hipMemcpyDeviceToHost);
@@ -626,6 +650,7 @@ extern "C" int lbm_server_destroy(lbm_server* s) {
     if (s->gexec) hipGraphExecDestroy(s->gexec);
     if (s->dtiles) hipFree(s->dtiles);
     if (s->dghosts) hipFree(s->dghosts);
+    if (s->dwalls) hipFree(s->dwalls);
     if (s->ev) hipEventDestroy(s->ev);
     if (s->hmirror) hipHostFree(s->hmirror);
     if (s->dtable) hipFree(s->dtable);
