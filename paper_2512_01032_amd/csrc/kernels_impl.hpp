@@ -530,10 +530,16 @@ template <typename T, int MODE>
 __global__ void __launch_bounds__(NTHREADS)
 wall_kernel(const Desc* __restrict__ descs, const WallRef* __restrict__ walls, int nwalls) {
     __shared__ T s_cs[2][16];   // cos and sin of each material's contact angle
-    const int k = blockIdx.x * NTHREADS + threadIdx.x;
+    // XCD-aware order: block b runs on XCD b mod 8; XCD c takes the c-th
+    // contiguous eighth of the list, so wall nodes that share phi lines
+    // (neighbouring rows and planes) meet in one L2
+    const int nb = gridDim.x, S = (nb + 7) / 8, r = nb - 8 * (S - 1);
+    const int c = blockIdx.x % 8, j = blockIdx.x / 8;
+    const int blk = c * (S - 1) + (c < r ? c : r) + j;
+    const int k = blk * NTHREADS + threadIdx.x;
     WallRef wr = {0, -1, 0, 0u};
     if (k < nwalls) wr = walls[k];
-    const int lat = uni(walls[blockIdx.x * NTHREADS].lat);
+    const int lat = uni(walls[blk * NTHREADS].lat);
     const Desc* D = descs + lat;
     if (threadIdx.x < 16) {
         s_cs[0][threadIdx.x] = (T)D->cos_t[threadIdx.x];
