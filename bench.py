@@ -353,6 +353,34 @@ def variants_leg(wl, args, torch):
     return out
 
 
+def streaming_leg(torch, gib=4, reps=10):
+    """Context for the roofline: the HBM rate plain streaming kernels reach on
+    this GPU, torch's vectorised elementwise kernels over gib-GiB FP32 tensors:
+    an in-place update (each byte read and written once, the traffic shape of
+    the in-place AA sweep) and a copy.  Timed with HIP events on torch's
+    stream."""
+    n = gib << 28
+    a = torch.empty(n, dtype=torch.float32, device="cuda")
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    out = {"tensor_GiB": gib}
+    for name, op in (("in_place_update_GBs", lambda: a.mul_(0.999)), ("copy_GBs", lambda: b.copy_(a))):
+        for _ in range(2):
+            op()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            op()
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = round(2.0 * 4 * n / (ms * 1e-3) / 1e9, 1)
+    del a, b
+    torch.cuda.empty_cache()
+    print("[bench] streaming ceiling: %s" % json.dumps(out), file=sys.stderr, flush=True)
+    return out
+
+
 def storage_bytes(storage):
     return {"fp64": (8, 8), "fp32": (4, 4), "fp32_shift": (4, 4),
             "fp16_shift_g": (4, 2), "fp16_shift_all": (2, 2)}[storage]
@@ -436,6 +464,7 @@ def main():
 
     primary = results["fp32_shift"]
     variants = variants_leg(wl, args, torch)
+    streaming = streaming_leg(torch)
     cpu = None
     errors = {}
     accuracy = None
@@ -496,6 +525,8 @@ def main():
                      "kernel": "sweep_kernel (fused stream-collide)",
                      "bytes_per_unit": b_alg, "unit_count": "fluid nodes per launch"},
         "cpu_baseline": cpu,
+        "streaming_ceiling": dict(streaming, sweep_frac_of_in_place=round(
+            primary["sweep_GBs"] / streaming["in_place_update_GBs"], 4)),
         "modes": {m: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
                   for m, r in results.items()},
         "max_abs_dphi_vs_oracle": errors,
