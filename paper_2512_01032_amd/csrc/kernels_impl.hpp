@@ -1,13 +1,17 @@
 // kernels_impl.hpp -- CDNA4 (gfx950) kernels of the phase-field LB step.
 //
-// Per time step two launches over a tile table (one lattice, or many lattices
-// of a serving batch):
+// Per time step, over a tile table (one lattice, or many lattices of a
+// serving batch) and a list of near-wall fluid nodes:
 //   phi pass : phi(x) = sum_i h_i(x) read in the current AA parity; a pressure
 //              ghost takes its owner's phi (Neumann).     (Sec. II.A, after Eq. 4)
+//   wall pass: at every near-wall fluid node the wall normal, the wetting
+//              values at the solid links (Eqs. 17-19, with the hysteresis
+//              blend of Sec. III.A) and the gradient / Laplacian sums with
+//              them (Eq. 16)
 //   sweep    : stages phi and node flags of each z-plane (tile + 1-node halo)
 //              in an LDS ring, then per fluid node
-//                - neighbour phi, wetting substitute at solid links (Eqs. 17-19)
-//                - isotropic gradient / Laplacian (Eq. 16)
+//                - isotropic gradient / Laplacian (Eq. 16); the wall pass's
+//                  sums at near-wall nodes
 //                - rho, mu (Eq. 9), tau_mix (Eqs. 10-12 and the Sec. III.A switch)
 //                - rho u, u, P (after Eq. 15)
 //                - filtered D3Q19 collision with K_i (Eqs. 6-8, 13-15)
@@ -17,20 +21,18 @@
 //                - pressure-ghost equilibria written by the ghost's owner
 //              FP64 wavefront/LDS reductions of mass, momentum, |u|max and
 //              phase pressures on diagnostic steps; the last tile of a lattice
-//              reduces the tile partials in a fixed order and advances the
-//              lattice's step counter.
+//              reduces the tile partials in a fixed order.
 //
-// AA pattern (one population array, updated in place).  At an even step node
-// x reads f_i from slot (x, i) and writes f*_i to (x, opp(i)); at an odd step
-// it reads f_i from (x - c_i, opp(i)) and writes f*_i to (x + c_i, i).  When
+// AA pattern (the populations are updated in place).  At an even step node x
+// reads f_i from slot (x, i) and writes f*_i to (x, opp(i)); at an odd step it
+// reads f_i from (x - c_i, opp(i)) and writes f*_i to (x + c_i, i).  When
 // x - c_i (x + c_i) is solid the odd-step access goes to the node's own slot
-// (x, i) ((x, opp(i))) instead, which realises the half-way bounce-back.  The
-// odd-step access to the solid node's slot is still issued (its value is
-// replaced or never read): every access then uses a scalar per-direction base
-// and wall nodes add a masked access to their own slot, rather than choosing a
-// base pointer per lane.  Every live slot is read and written by one node
-// only, so the sweep needs no second lattice and no synchronisation between
-// tiles.  The parity is a template argument; all lattices of a launch share it.
+// (x, i) ((x, opp(i))) instead, which realises the half-way bounce-back; the
+// two candidate slots of an access share a buffer resource, so each lane
+// picks its slot by its offset within one access.  Every live slot is read
+// and written by one node only, so the sweep needs no second lattice and no
+// synchronisation between tiles.  The parity is a template argument; all
+// lattices of a launch share it.
 //
 // Arithmetic of the FP32 storage modes is FP32 and written in deviation form:
 // with f_i = w_i f_ref + d_i the moments use d_i only (sum_i w_i c_i = 0), so
