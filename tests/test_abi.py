@@ -166,3 +166,30 @@ def test_footprint_counts_populations():
     import dataclasses
     wl.phys = dataclasses.replace(wl.phys, q_phase=19)
     assert lbm.footprint(wl, "fp32_shift") - f32 >= n * 12 * 4
+
+
+def test_population_layout_limits():
+    """Populations sit in 64-node blocks with rows padded to 64 nodes, in one
+    buffer group while a node's populations take at most 104 bytes, else in
+    two; each group is addressed with 32-bit offsets, so a lattice whose
+    group exceeds 4 GiB is rejected (lbm_footprint returns 0)."""
+    from paper_2512_01032_amd import inputs, lbm
+    wl = inputs.random_small(8, 6, 5, seed=0)
+    p = lbm.params_from_workload(wl)
+
+    def fp(nx, ny, nz, storage):
+        p.nx, p.ny, p.nz = nx, ny, nz
+        p.storage = lbm.STORAGE[storage]
+        return lbm.lbm_footprint(ctypes.byref(p))
+
+    # a 40-wide row stores 64 nodes of populations
+    assert fp(40, 16, 16, "fp32_shift") >= 64 * 16 * 16 * 104
+    # FP32 on D3Q7: 104 bytes per node in one group, 2^32 / 104 nodes at most
+    assert fp(256, 256, 630, "fp32_shift") > 0
+    assert fp(256, 256, 631, "fp32_shift") == 0
+    # FP64: two groups of 104 bytes per node, the same node limit
+    assert fp(256, 256, 630, "fp64") > 0
+    assert fp(256, 256, 631, "fp64") == 0
+    # FP16 g: 66 bytes per node in one group
+    assert fp(256, 256, 992, "fp16_shift_g") > 0
+    assert fp(256, 256, 993, "fp16_shift_g") == 0
