@@ -163,3 +163,26 @@ def test_alone_equals_mix_bitwise_with_subvoxel_walls():
         wl.steps = 17
     res = _serve(lbm, wls, hbm_budget=1 << 30, use_graph=True, ticks_per_sync=6)
     _check_same(lbm, wls, res)
+
+
+def test_alone_equals_mix_bitwise_with_hysteresis():
+    """Lattices with contact-angle hysteresis (both readings) batched with
+    plain ones: the wall pass over the concatenated near-wall lists updates
+    each lattice's own history, so every result is still bitwise the request
+    run alone."""
+    import dataclasses
+    from paper_2512_01032_amd import inputs
+    lbm = _lbm()
+    wls = [
+        inputs.random_small(40, 12, 10, seed=8, walls=True, open_x=True, optimised_model=True,
+                            u_amp=0.002, storage="fp32_shift"),
+        inputs.random_small(40, 12, 10, seed=9, walls=True, open_x=True, optimised_model=True,
+                            u_amp=0.002, storage="fp32_shift"),
+        inputs.droplet_on_wall(32, 50.0, 21),
+    ]
+    for k, mode in ((0, 1), (1, 2)):
+        wls[k].phys = dataclasses.replace(wls[k].phys, hysteresis=mode, hyst_beta=0.95)
+        wls[k].name += "_hyst%d" % mode
+        wls[k].steps = 19
+    res = _serve(lbm, wls, hbm_budget=1 << 30, use_graph=True, ticks_per_sync=6)
+    _check_same(lbm, wls, res)
