@@ -170,10 +170,15 @@ typedef struct lbm_diag {
 typedef struct lbm_handle lbm_handle;
 
 /* Bytes of device memory one lattice needs (populations, phi, flags, tile
- * table and reduction partials).  0 if the parameters are invalid.  With
- * hysteresis the wall-value history is sized as if every node had wall links
- * (the geometry is not known here): an upper bound; lbm_create allocates the
- * exact amount when it allocates itself. */
+ * table, reduction partials and the near-wall arrays).  0 if the parameters
+ * are invalid, including a lattice whose populations exceed what 32-bit
+ * offsets address: populations are stored in blocks of 64 nodes with rows
+ * padded to 64 nodes, in one group of at most 4 GiB while a node's
+ * populations take at most 104 bytes, else in two (about 41 M nodes in FP32
+ * or FP64 on D3Q7).  The near-wall arrays (and the hysteresis history) are
+ * sized as if every node had wall links (the geometry is not known here): an
+ * upper bound; lbm_create allocates the exact amount when it allocates
+ * itself. */
 size_t lbm_footprint(const lbm_params *p);
 
 /* Validate, allocate (or carve the arena), upload geometry and initial state
@@ -184,7 +189,8 @@ int lbm_create(const lbm_params *p, const lbm_geometry *geo, const lbm_init *ini
                const lbm_device_ctx *ctx, lbm_handle **out);
 
 /* Queue nsteps time steps on the handle's stream and return.  Each step is
- * the phi pass followed by the fused stream-collide sweep.  Returns
+ * the phi pass, the wall pass (wetting values and stencil sums of the
+ * near-wall nodes, Sec. II.B) and the fused stream-collide sweep.  Returns
  * LBM_E_UNSTABLE if a diagnostic taken before this call flagged NaN or
  * |u| > u_max (sticky). */
 int lbm_step(lbm_handle *h, int64_t nsteps);
