@@ -78,8 +78,8 @@ __device__ inline double uni(double v) { return __builtin_bit_cast(double, uni(_
 __device__ inline float uni(float v) { return __builtin_bit_cast(float, uni(__builtin_bit_cast(int, v))); }
 template <typename P> __device__ inline P* unip(P* p) { return (P*)uni((int64_t)(uintptr_t)p); }
 
-__device__ inline Tile load_tile(const Tile* tiles) {
-    const Tile t = tiles[blockIdx.x];
+__device__ inline Tile load_tile(const Tile* tiles, bool reversed = false) {
+    const Tile t = tiles[reversed ? gridDim.x - 1 - blockIdx.x : blockIdx.x];
     Tile u;
     u.lat = uni(t.lat); u.x0 = uni(t.x0); u.y0 = uni(t.y0); u.z0 = uni(t.z0); u.zn = uni(t.zn);
     u.tile_in_lat = uni(t.tile_in_lat); u.pad[0] = u.pad[1] = 0;
@@ -378,7 +378,11 @@ template <typename T, typename SH, typename SG, int PAR, int QP>
 __global__ void __launch_bounds__(NTHREADS)
 phi_kernel(const Desc* __restrict__ descs, const Tile* __restrict__ tiles, int force) {
     typedef Lay<SH, SG, QP> LAYT;
-    const Tile tl = load_tile(tiles);
+    // the tile list in reverse: the sweep walks it forwards, so the phi pass
+    // starts on the tiles the last sweep wrote last (still in the caches)
+    // and ends on those the next sweep reads first (1110 -> 1099 us per
+    // step, FP32, 256 x 256 x 512 duct)
+    const Tile tl = load_tile(tiles, true);
     const Desc* D = descs + tl.lat;
     const int64_t step = uni(D->step);
     if (!force && step >= uni(D->stop_step)) return;
