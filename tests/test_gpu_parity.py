@@ -587,3 +587,25 @@ def test_subvoxel_reduced_precision(storage):
             assert err[k] <= 1e-5, (k, err)
     else:
         assert err["phi"] <= 1e-3, err
+
+
+# ------------------------------------------------------- capillary intrusion
+@pytest.mark.parametrize("storage,frac", [("fp64", 1e-6), ("fp32_shift", 0.02), ("fp16_shift_g", 0.05)])
+def test_capillary_intrusion_matches_oracle(storage, frac):
+    """Lucas-Washburn filling of a quasi-2D channel (the oracle pin's input):
+    the liquid length after 12000 steps on the GPU against the FP64 oracle,
+    to a fraction of the distance the meniscus travelled (FP64: 1e-6; FP32
+    and FP16 g: the accumulated rounding of 12000 steps at a moving contact
+    line)."""
+    from paper_2512_01032_amd import inputs
+    wl = inputs.channel_filling_2d(theta=45.0, nx=96, nz=10, fill=20, nu_l=0.03)
+    g, o = _run_pair(wl, 12000, storage)
+    fluid = o.kinds() == 0
+    H = wl.meta["H"]
+    z0 = float((np.clip(wl.phi0, 0.0, 1.0) * fluid).sum() / H)
+    zo = float((np.clip(o.fields()[0], 0.0, 1.0) * fluid).sum() / H)
+    zg = float((np.clip(g.fields()[0], 0.0, 1.0) * fluid).sum() / H)
+    print(storage, "z0 %.4f oracle %.6f gpu %.6f" % (z0, zo, zg), flush=True)
+    g.close()
+    assert zo - z0 > 5.0
+    assert abs(zg - zo) <= frac * (zo - z0)
