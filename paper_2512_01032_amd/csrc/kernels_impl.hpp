@@ -671,6 +671,9 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
     __shared__ uint8_t s_flag[4][LN];
     __shared__ double s_red[NPART][NTHREADS / 64];
     __shared__ int s_last;
+    // sub-voxel instance: f_i^in of each solid link i, kept by the thread
+    // that read it from the stream step to its write-back
+    __shared__ T s_fin[SV ? QG - 1 : 1][NTHREADS];
 
     const Tile tl = load_tile(tiles);
     Desc* D = descs + tl.lat;
@@ -820,7 +823,35 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
         const bool svx = uni(D->subvoxel) != 0;
         const T* __restrict__ wtab = nullptr;
         const int64_t wsl = wslot_cur, wstr = uni(D->n_wall);
-        if (solid && svx) wtab = unip((const T*)D->wall);
+        if (SV && MODE == MODE_STEP && solid && svx) {
+            wtab = unip((const T*)D->wall);
+            // Even steps load the wall fractions at the write-back.  Odd
+            // steps (fewer registers to spare) keep the fraction of a pair
+            // (i, ibar) with one solid link in the LDS slot of its fluid
+            // partner until the write-back (the solid link's own slot takes
+            // f_i^in); pairs with both links solid reload theirs there.
+            // 4-byte fractions go straight from memory to LDS (no registers
+            // held, no wait here), FP64 ones through registers.
+            if constexpr (PAR == 1 && sizeof(T) == 4) {
+#pragma unroll
+                for (int i = 1; i < QG; i += 2) {
+                    const bool si = (solid >> i) & 1u, sj = (solid >> (i + 1)) & 1u;
+                    // destination: row of the partner link, the wave's 64 lanes
+                    if (si && !sj)
+                        __builtin_amdgcn_global_load_lds((const void*)(wtab + (int64_t)(i - 1) * wstr + wsl),
+                                                         (void*)&s_fin[i][tid & ~63], 4, 0, 0);
+                    if (sj && !si)
+                        __builtin_amdgcn_global_load_lds((const void*)(wtab + (int64_t)i * wstr + wsl),
+                                                         (void*)&s_fin[i - 1][tid & ~63], 4, 0, 0);
+                }
+            } else {
+#pragma unroll
+                for (int i = 1; i < QG && PAR == 1; i += 2) {
+                    const bool si = (solid >> i) & 1u, sj = (solid >> (i + 1)) & 1u;
+                    if (si != sj) s_fin[si ? i : i - 1][tid] = wtab[(int64_t)(si ? i - 1 : i) * wstr + wsl];
+                }
+            }
+        }
         if (solid) {
             // wetting (Eqs. 17-19): the stencil sums with the wall values and
             // the wall normal come from the wall pass
@@ -852,6 +883,11 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
         } else {
             T dg[QG];
             read_pops<T, PAR>(gb, nb, solid, ph[PI_INV_SG], dg);
+            if (SV && MODE == MODE_STEP && svx && solid) {
+#pragma unroll
+                for (int i = 1; i < QG; ++i)
+                    if ((solid >> i) & 1u) s_fin[i - 1][tid] = dg[i];
+            }
             // pairs (i, opp(i)): even part feeds mass and second moments, odd
             // part the momentum; u first (it needs only g and phi), then P
             T s = dg[0], j[3] = {T(0), T(0), T(0)};
@@ -952,39 +988,6 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
             st.om = (T(1) - dev_div(T(1), tau)) * i2Tg2;
         }
         const T sg = ph[PI_SG];
-        // ---- sub-voxel walls (MODE_STEP): linear interpolated bounce-back of
-        //      g (after the write-back, below) needs f_i^in, the population
-        //      that entered the node along c_i this step, for every solid link
-        //      i; the write-back overwrites its slot, so it is parked first
-        //      where nothing else reads or writes during this step: an odd
-        //      step in the node's own slot (x, ibar), the final destination,
-        //      which the odd write-back does not touch; an even step in the
-        //      solid neighbour's slot (x + c_i, i).
-        if (SV && MODE == MODE_STEP && svx && solid) {
-            if (PAR == 1) {
-                // f_i^in sits in (x - c_i, ibar), or in (x, i) where x - c_i is
-                // solid, and is parked in (x, ibar).  With both ends of a pair
-                // solid (a one-node gap) each link's source is the other's
-                // destination, so a pair is loaded before it is stored.
-                for (int i = 1; i < QG; i += 2) {
-                    const int j = i + 1;                          // OPP[i]
-                    const bool si = (solid >> i) & 1u, sj = (solid >> j) & 1u;
-                    if (!si && !sj) continue;
-                    SG fi_in = SG(0), fj_in = SG(0);
-                    if (si) fi_in = (SG)(sj ? Store<SG>::ld(gb, i, gown)
-                                            : Store<SG>::ld(gb, j, nb.at<true>(-CX[i], -CY[i], -CZ[i])));
-                    if (sj) fj_in = (SG)(si ? Store<SG>::ld(gb, j, gown)
-                                            : Store<SG>::ld(gb, i, nb.at<true>(-CX[j], -CY[j], -CZ[j])));
-                    if (si) Store<SG>::st(gb, j, gown, fi_in);
-                    if (sj) Store<SG>::st(gb, i, gown, fj_in);
-                }
-            } else {
-                // f_i^in sits in the own slot (x, i); parked in (x + c_i, i)
-                for (int i = 1; i < QG; ++i)
-                    if ((solid >> i) & 1u)
-                        Store<SG>::st(gb, i, nb.at<true>(CX[i], CY[i], CZ[i]), Store<SG>::ld(gb, i, gown));
-            }
-        }
         // D3Q19 write-back (AA slots of parity PAR)
         // free-slip band (Sec. III.A): at a wall link the wall moves with the
         // tangential fluid velocity u_w, and the bounced-back population
@@ -1005,24 +1008,62 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
         // write-back: half-way bounce-back at wall links through the slot
         // choice of put_pop (even: the own slot (x, ibar) anyway; odd: (x, ibar)
         // instead of the solid node's (x + c_i, i)), with the moving-wall term
-        // applied in registers.  The sub-voxel instance stores every value
-        // at its unbounded AA slot and fixes the wall links afterwards.
+        // applied in registers
         auto put_g = [&](int i, T v) {
-            if (MODE == MODE_STEP && !SV && slip && i > 0 && ((solid >> i) & 1u)) v -= mwall(i);
+            if (MODE == MODE_STEP && !(SV && svx) && slip && i > 0 && ((solid >> i) & 1u)) v -= mwall(i);
             const T vs = Store<SG>::scaled ? v * sg : v;
-            if (MODE == MODE_STEP) {
-                if (!SV) put_pop<PAR>(gb, nb, solid, i, vs);
-                else if (PAR == 0 || i == 0) Store<SG>::st(gb, OPP[i], gown, vs);
-                else Store<SG>::st(gb, i, nb.at<true>(CX[i], CY[i], CZ[i]), vs);
-            } else {
-                place_pop<PAR>(gb, nb, solid, i, vs);
+            if (MODE == MODE_STEP) put_pop<PAR>(gb, nb, solid, i, vs);
+            else place_pop<PAR>(gb, nb, solid, i, vs);
+        };
+        // sub-voxel walls (Sec. III.A): the value returned along ibar for a
+        // solid link i is the linear interpolated bounce-back at the link's
+        // wall fraction q, formed from the pair's post-collision values in
+        // registers and f_i^in from LDS:
+        //   q >= 1/2: (g*_i - m) / (2q) + (1 - 1/(2q)) g*_ibar
+        //   q <  1/2: 2q g*_i + (1 - 2q) f_i^in - m
+        // (m: moving-wall term), and stored where the half-way rule puts g*_i
+        const bool svw = SV && MODE == MODE_STEP && svx && solid;
+        constexpr bool QREG = PAR == 0;   // fractions in registers
+        T qv[QG];
+        if (QREG && svw) {
+#pragma unroll
+            for (int i = 1; i < QG; ++i)
+                qv[i] = ((solid >> i) & 1u) ? wtab[(int64_t)(i - 1) * wstr + wsl] : T(0);
+        }
+        // the memory-to-LDS copies are counted by vmcnt only
+        if (PAR == 1 && sizeof(T) == 4 && svw) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        auto bb_value = [&](int i, T q, T gi, T gibar) -> T {
+            const T m = slip ? mwall(i) : T(0);
+            if (q >= T(0.5)) {
+                const T r = dev_div(T(1), T(2) * q);
+                return (gi - m) * r + (T(1) - r) * gibar;
             }
+            return T(2) * q * gi + (T(1) - T(2) * q) * s_fin[i - 1][tid] - m;
         };
         put_g(0, g_out<T, MODE>(0, st, rdif));
 #pragma unroll
         for (int i = 1; i < QG; i += 2) {
             T vp, vm;
             g_out_pair<T, MODE>(i, st, rdif, vp, vm);
+            if (svw) {
+                const bool si = (solid >> i) & 1u, sj = (solid >> (i + 1)) & 1u;
+                if (si || sj) {
+                    T qi, qj;
+                    if (QREG) {
+                        qi = qv[i];
+                        qj = qv[i + 1];
+                    } else if (si && sj) {
+                        qi = wtab[(int64_t)(i - 1) * wstr + wsl];
+                        qj = wtab[(int64_t)i * wstr + wsl];
+                    } else {
+                        qi = qj = s_fin[si ? i : i - 1][tid];
+                    }
+                    const T wp_i = si ? bb_value(i, qi, vp, vm) : vp;
+                    const T wm_i = sj ? bb_value(i + 1, qj, vm, vp) : vm;
+                    vp = wp_i;
+                    vm = wm_i;
+                }
+            }
             put_g(i, vp);
             put_g(i + 1, vm);
         }
@@ -1066,58 +1107,6 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
             }
             if (MODE == MODE_STEP) write_pops<T, PAR>(hb, nb, solid, ph[PI_SH], B);
             else place_pops<T, PAR>(hb, nb, solid, ph[PI_SH], B);
-        }
-
-        // ---- sub-voxel instance: wall links (Sec. III.A).  The value returned
-        //      along ibar goes to the node's own slot (x, ibar): the even
-        //      write-back put g*_i there, the odd one into the solid node's
-        //      slot (x + c_i, i), never read.  The post-collision values are
-        //      read back from where the write-back stored them (slots only
-        //      this node writes during the step) rather than recomputed.
-        if (SV && MODE == MODE_STEP && solid) {
-            {
-                const T isg = ph[PI_INV_SG];
-                auto back = [&](int q, uint32_t node) -> T {
-                    const T v = (T)Store<SG>::ld(gb, q, node);
-                    return Store<SG>::scaled ? v * isg : v;
-                };
-                if ((SV && svx) || PAR == 1 || slip) {
-                    // value returned along ibar for solid link i (reads only)
-                    auto wall_value = [&](int i) -> T {
-                        const T m = mwall(i);                         // moving-wall term
-                        // g*_i: even (x, ibar), odd (x + c_i, i)
-                        const T fi = PAR == 0 ? back(OPP[i], gown)
-                                              : back(i, nb.at<true>(CX[i], CY[i], CZ[i]));
-                        if (!(SV && svx)) return fi - m;
-                        // linear interpolated bounce-back at the wall fraction q
-                        // of link i (f_i^in parked above):
-                        //   q >= 1/2: g*_i / (2q) + (1 - 1/(2q)) g*_ibar - m / (2q)
-                        //   q <  1/2: 2q g*_i + (1 - 2q) f_i^in - m
-                        const T q = wtab[(int64_t)(i - 1) * wstr + wsl];
-                        if (q >= T(0.5)) {
-                            // g*_ibar: even (x, i), odd (x - c_i, ibar)
-                            const T fo = PAR == 0 ? back(i, gown)
-                                                  : back(OPP[i], nb.at<true>(-CX[i], -CY[i], -CZ[i]));
-                            const T r = dev_div(T(1), T(2) * q);
-                            return (fi - m) * r + (T(1) - r) * fo;
-                        }
-                        const T fin = PAR == 1 ? back(OPP[i], gown)
-                                               : back(i, nb.at<true>(CX[i], CY[i], CZ[i]));
-                        return T(2) * q * fi + (T(1) - T(2) * q) * fin - m;
-                    };
-                    // a pair (i, ibar) with both ends solid reads the slots the
-                    // other writes: both values are formed before either store
-                    for (int i = 1; i < QG; i += 2) {
-                        const int j = i + 1;                          // OPP[i]
-                        const bool si = (solid >> i) & 1u, sj = (solid >> j) & 1u;
-                        if (!si && !sj) continue;
-                        const T vi = si ? wall_value(i) : T(0);
-                        const T vj = sj ? wall_value(j) : T(0);
-                        if (si) Store<SG>::st(gb, j, gown, Store<SG>::scaled ? vi * sg : vi);
-                        if (sj) Store<SG>::st(gb, i, gown, Store<SG>::scaled ? vj * sg : vj);
-                    }
-                }
-            }
         }
 
         // ---- pressure ghosts owned by this node: hand this step's u to the
