@@ -874,6 +874,7 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
 
         // ---- moments of the populations entering the collision
         T m[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};   // sum c c d: xx yy zz xy xz yz
+        T qv[QG];   // sub-voxel even steps: wall fractions of the solid links
         if (MODE == MODE_INIT) {
             const double* ui = in.u;
             st.u[0] = ui ? (T)ui[n] : T(0);
@@ -887,6 +888,11 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
 #pragma unroll
                 for (int i = 1; i < QG; ++i)
                     if ((solid >> i) & 1u) s_fin[i - 1][tid] = dg[i];
+                if (PAR == 0) {
+#pragma unroll
+                    for (int i = 1; i < QG; ++i)
+                        qv[i] = ((solid >> i) & 1u) ? wtab[(int64_t)(i - 1) * wstr + wsl] : T(0);
+                }
             }
             // pairs (i, opp(i)): even part feeds mass and second moments, odd
             // part the momentum; u first (it needs only g and phi), then P
@@ -1024,12 +1030,6 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
         // (m: moving-wall term), and stored where the half-way rule puts g*_i
         const bool svw = SV && MODE == MODE_STEP && svx && solid;
         constexpr bool QREG = PAR == 0;   // fractions in registers
-        T qv[QG];
-        if (QREG && svw) {
-#pragma unroll
-            for (int i = 1; i < QG; ++i)
-                qv[i] = ((solid >> i) & 1u) ? wtab[(int64_t)(i - 1) * wstr + wsl] : T(0);
-        }
         // the memory-to-LDS copies are counted by vmcnt only
         if (PAR == 1 && sizeof(T) == 4 && svw) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         auto bb_value = [&](int i, T q, T gi, T gibar) -> T {
