@@ -76,7 +76,13 @@ __device__ inline int64_t uni(int64_t v) {
 }
 __device__ inline double uni(double v) { return __builtin_bit_cast(double, uni(__builtin_bit_cast(int64_t, v))); }
 __device__ inline float uni(float v) { return __builtin_bit_cast(float, uni(__builtin_bit_cast(int, v))); }
-template <typename P> __device__ inline P* unip(P* p) { return (P*)uni((int64_t)(uintptr_t)p); }
+// Every pointer held in a descriptor points to device (global) memory: the
+// cast through address space 1 lets the compiler use global instead of flat
+// loads and stores (flat ones also count as LDS traffic, so each wait for an
+// LDS result would wait for them too).
+template <typename P> __device__ inline P* unip(P* p) {
+    return (P*)(__attribute__((address_space(1))) P*)uni((int64_t)(uintptr_t)p);
+}
 
 __device__ inline Tile load_tile(const Tile* tiles, bool reversed = false) {
     const Tile t = tiles[reversed ? gridDim.x - 1 - blockIdx.x : blockIdx.x];
