@@ -890,15 +890,10 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
         } else {
             T dg[QG];
             read_pops<T, PAR>(gb, nb, solid, ph[PI_INV_SG], dg);
-            if (SV && MODE == MODE_STEP && svx && solid) {
+            if (SV && MODE == MODE_STEP && svx && solid && PAR == 0) {
 #pragma unroll
                 for (int i = 1; i < QG; ++i)
-                    if ((solid >> i) & 1u) s_fin[i - 1][tid] = dg[i];
-                if (PAR == 0) {
-#pragma unroll
-                    for (int i = 1; i < QG; ++i)
-                        qv[i] = ((solid >> i) & 1u) ? wtab[(int64_t)(i - 1) * wstr + wsl] : T(0);
-                }
+                    qv[i] = ((solid >> i) & 1u) ? wtab[(int64_t)(i - 1) * wstr + wsl] : T(0);
             }
             // pairs (i, opp(i)): even part feeds mass and second moments, odd
             // part the momentum; u first (it needs only g and phi), then P
@@ -916,6 +911,13 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
                 if (CX[i] * CY[i]) m[3] += T(CX[i] * CY[i]) * ev;
                 if (CX[i] * CZ[i]) m[4] += T(CX[i] * CZ[i]) * ev;
                 if (CY[i] * CZ[i]) m[5] += T(CY[i] * CZ[i]) * ev;
+            }
+            // sub-voxel walls: f_i^in of each solid link waits in LDS for the
+            // write-back (stored once every population has arrived)
+            if (SV && MODE == MODE_STEP && svx && solid) {
+#pragma unroll
+                for (int i = 1; i < QG; ++i)
+                    if ((solid >> i) & 1u) s_fin[i - 1][tid] = dg[i];
             }
             const T irho = dev_div(T(1), st.rho);
             st.u[0] = (j[0] + T(0.5) * (mu * st.grad[0] + ph[PI_FX])) * irho;
@@ -1046,6 +1048,16 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
             }
             return T(2) * q * gi + (T(1) - T(2) * q) * s_fin[i - 1][tid] - m;
         };
+        // the same without branches, as a (g*_i - m) + (1 - a) x:
+        //   q >= 1/2: a = 1/(2q), x = g*_ibar;   q < 1/2: a = 2q, x = f_i^in - m
+        auto bb_value_sel = [&](int i, T q, T gi, T gibar) -> T {
+            const T m = mwall(i);   // zero outside the slip band (u_w = 0)
+            const T q2 = T(2) * q;
+            const bool hi = q2 >= T(1);
+            const T a = hi ? dev_div(T(1), q2) : q2;
+            const T x = hi ? gibar : s_fin[i - 1][tid] - m;
+            return a * (gi - m) + (T(1) - a) * x;
+        };
         put_g(0, g_out<T, MODE>(0, st, rdif));
 #pragma unroll
         for (int i = 1; i < QG; i += 2) {
@@ -1053,21 +1065,33 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
             g_out_pair<T, MODE>(i, st, rdif, vp, vm);
             if (svw) {
                 const bool si = (solid >> i) & 1u, sj = (solid >> (i + 1)) & 1u;
-                if (si || sj) {
-                    T qi, qj;
-                    if (QREG) {
-                        qi = qv[i];
-                        qj = qv[i + 1];
-                    } else if (si && sj) {
-                        qi = wtab[(int64_t)(i - 1) * wstr + wsl];
-                        qj = wtab[(int64_t)i * wstr + wsl];
-                    } else {
-                        qi = qj = s_fin[si ? i : i - 1][tid];
+                if (QREG) {
+                    // even steps: only the solid links (registers are short)
+                    if (si || sj) {
+                        const T wp_i = si ? bb_value(i, qv[i], vp, vm) : vp;
+                        const T wm_i = sj ? bb_value(i + 1, qv[i + 1], vm, vp) : vm;
+                        vp = wp_i;
+                        vm = wm_i;
                     }
-                    const T wp_i = si ? bb_value(i, qi, vp, vm) : vp;
-                    const T wm_i = sj ? bb_value(i + 1, qj, vm, vp) : vm;
-                    vp = wp_i;
-                    vm = wm_i;
+                } else {
+                    // odd steps: both links formed, those not solid dropped
+                    // (fewer branches).  A pair with both links solid reloads
+                    // its fractions and uses them in its own branch, so that
+                    // only waves holding one wait for the loads (the wait
+                    // also covers every store issued before).
+                    if (si && sj) {
+                        const T qi = wtab[(int64_t)(i - 1) * wstr + wsl];
+                        const T qj = wtab[(int64_t)i * wstr + wsl];
+                        const T wp_i = bb_value_sel(i, qi, vp, vm);
+                        vm = bb_value_sel(i + 1, qj, vm, vp);
+                        vp = wp_i;
+                    } else {
+                        const T q = s_fin[si ? i : i - 1][tid];
+                        const T wp_i = bb_value_sel(i, q, vp, vm);
+                        const T wm_i = bb_value_sel(i + 1, q, vm, vp);
+                        vp = si ? wp_i : vp;
+                        vm = sj ? wm_i : vm;
+                    }
                 }
             }
             put_g(i, vp);
