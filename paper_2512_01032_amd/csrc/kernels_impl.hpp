@@ -198,17 +198,19 @@ __device__ inline PopArray<S, Q, U0, LAY> pop_array(const Desc* D) {
 
 // ----------------------------------------------------------- parameters
 // Derived constants come precomputed in the compute precision (Desc::pf for
-// FP32, Desc::pd for FP64) and are read through a uniform pointer, so they
-// live in scalar registers.
+// FP32, Desc::pd for FP64).  No kernel writes them, so they are read through
+// the constant address space: scalar loads, which the compiler may repeat
+// anywhere (vector loads of them would be counted with the population
+// stores, and each wait for one would wait for every store before it).
 template <typename T> __device__ inline const T* param_block(const Desc* D);
 template <> __device__ inline const float* param_block<float>(const Desc* D) { return D->pf; }
 template <> __device__ inline const double* param_block<double>(const Desc* D) { return D->pd; }
 
 template <typename T> struct Phys {
-    const T* __restrict__ p;
+    const __attribute__((address_space(4))) T* p;
     int mobility_corr, mix, friction;
     __device__ void load(const Desc* D) {
-        p = unip(param_block<T>(D));
+        p = (const __attribute__((address_space(4))) T*)uni((int64_t)(uintptr_t)param_block<T>(D));
         mobility_corr = uni(D->mobility_corr);
         mix = uni(D->mix);
         friction = uni(D->friction);
@@ -766,6 +768,19 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
             for (int j = 0; j < NST; ++j)
                 if (coff[j] >= 0) { nv[j] = phig[coff[j] + zo]; nf[j] = flg[coff[j] + zo]; }
         }
+        // the staged plane goes to the free ring slot (k + 3) & 3 as soon as
+        // the node's populations have arrived (then the loads issued before
+        // them have too), before the node's stores: a wait for the plane
+        // after the stores would also wait for every store
+        bool staged = !more;
+        auto stage_next = [&]() {
+            if (staged) return;
+            const int m = (k + 3) & 3;
+#pragma unroll
+            for (int j = 0; j < NST; ++j)
+                if (coff[j] >= 0) { s_phi[m][tid + j * NTHREADS] = nv[j]; s_flag[m][tid + j * NTHREADS] = nf[j]; }
+            staged = true;
+        };
         const uint32_t links = lk_next;
         const int32_t wslot_cur = ws_next;
         lk_next = 0u;
@@ -912,6 +927,7 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
                 if (CX[i] * CZ[i]) m[4] += T(CX[i] * CZ[i]) * ev;
                 if (CY[i] * CZ[i]) m[5] += T(CY[i] * CZ[i]) * ev;
             }
+            stage_next();
             // sub-voxel walls: f_i^in of each solid link waits in LDS for the
             // write-back (stored once every population has arrived)
             if (SV && MODE == MODE_STEP && svx && solid) {
@@ -1156,12 +1172,7 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
             }
         }
         } while (0);
-        if (more) {
-            const int m = (k + 3) & 3;
-#pragma unroll
-            for (int j = 0; j < NST; ++j)
-                if (coff[j] >= 0) { s_phi[m][tid + j * NTHREADS] = nv[j]; s_flag[m][tid + j * NTHREADS] = nf[j]; }
-        }
+        stage_next();
         __syncthreads();
     }
 
