@@ -80,6 +80,15 @@ __device__ inline float uni(float v) { return __builtin_bit_cast(float, uni(__bu
 // cast through address space 1 lets the compiler use global instead of flat
 // loads and stores (flat ones also count as LDS traffic, so each wait for an
 // LDS result would wait for them too).
+// Workgroup barrier that orders LDS only.  Within one sweep the threads of a
+// block share nothing through global memory (each population slot read or
+// written during a step is touched by one node only), so the barrier need not
+// wait for the population stores in flight, which a full __syncthreads would.
+__device__ inline void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 template <typename P> __device__ inline P* unip(P* p) {
     return (P*)(__attribute__((address_space(1))) P*)uni((int64_t)(uintptr_t)p);
 }
@@ -745,7 +754,7 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
     stage(0, tl.z0 - 1);
     stage(1, tl.z0);
     stage(2, tl.z0 + 1);
-    __syncthreads();
+    lds_barrier();
     const int c0 = (ty + 1) * LW + (tx + 1);
     // link word of the node (solid-link mask, owned ghost faces), fetched one
     // plane ahead from the staged flags: the odd step's population addresses
@@ -1173,7 +1182,7 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
         }
         } while (0);
         stage_next();
-        __syncthreads();
+        lds_barrier();
     }
 
     // Only a diagnostic pass needs tiles to meet: a cross-tile handshake costs
