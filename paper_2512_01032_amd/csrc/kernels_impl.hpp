@@ -761,6 +761,9 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
     // depend on it
     constexpr uint8_t LINKED = F_NEAR_WALL | F_OWNER;
     const int32_t* __restrict__ wsl_arr = unip(D->wslot);
+    // descriptor fields the plane loop reads, through the constant address
+    // space (scalar loads; the sweep writes none of them)
+    const __attribute__((address_space(4))) Desc* DC = (const __attribute__((address_space(4))) Desc*)D;
     uint32_t lk_next = 0u;
     int32_t ws_next = 0;
     if (active && (s_flag[1][c0] & LINKED)) lk_next = lnk[x + nx * y + nxy * tl.z0];
@@ -768,6 +771,12 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
     for (int k = 0; k < tl.zn; ++k) {
         const int z = tl.z0 + k;
         const bool more = k + 1 < tl.zn;
+        // this plane's link word and wall slot (loaded one plane ahead) are
+        // taken here, before the next plane's loads are issued: a wait for
+        // them later would also wait for those loads
+        const uint32_t links = lk_next;
+        const int32_t wslot_cur = ws_next;
+        asm volatile("" ::"v"(links), "v"(wslot_cur));
         T nv[NST];
         uint8_t nf[NST];
         if (more) {
@@ -790,8 +799,6 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
                 if (coff[j] >= 0) { s_phi[m][tid + j * NTHREADS] = nv[j]; s_flag[m][tid + j * NTHREADS] = nf[j]; }
             staged = true;
         };
-        const uint32_t links = lk_next;
-        const int32_t wslot_cur = ws_next;
         lk_next = 0u;
         ws_next = 0;
         if (more && active) {
@@ -850,11 +857,11 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
         for (int i = 1; i < 19; i += 2) pair_sum(i, nbv(i), nbv(i + 1));
         T nw[3] = {T(0), T(0), T(0)};
         // sub-voxel walls: per-slot table of link fractions and wall normal
-        const bool svx = uni(D->subvoxel) != 0;
+        const bool svx = DC->subvoxel != 0;
         const T* __restrict__ wtab = nullptr;
-        const int64_t wsl = wslot_cur, wstr = uni(D->n_wall);
+        const int64_t wsl = wslot_cur, wstr = DC->n_wall;
         if (SV && MODE == MODE_STEP && solid && svx) {
-            wtab = unip((const T*)D->wall);
+            wtab = unip((const T*)DC->wall);
             // Even steps load the wall fractions at the write-back.  Odd
             // steps (fewer registers to spare) keep the fraction of a pair
             // (i, ibar) with one solid link in the LDS slot of its fluid
@@ -885,7 +892,7 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
         if (solid) {
             // wetting (Eqs. 17-19): the stencil sums with the wall values and
             // the wall normal come from the wall pass
-            const T* __restrict__ wgl = unip((const T*)D->wgl);
+            const T* __restrict__ wgl = unip((const T*)DC->wgl);
             gx = wgl[wsl];
             gy = wgl[wstr + wsl];
             gz = wgl[2 * wstr + wsl];
@@ -1167,8 +1174,8 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
         // ---- pressure ghosts owned by this node: hand this step's u to the
         //      ghost pass (phi of the owner already sits in the ghost's phi entry)
         if (MODE == MODE_STEP && (links >> LINK_OWNER_SHIFT)) {
-            T* __restrict__ gbuf = (T*)D->gbuf;
-            const int64_t gc = D->gface_count;
+            T* __restrict__ gbuf = unip((T*)DC->gbuf);
+            const int64_t gc = DC->gface_count;
             for (int face = 0; face < 6; ++face) {
                 if (!((links >> (LINK_OWNER_SHIFT + face)) & 1u)) continue;
                 const int ax = face >> 1, sgn = (face & 1) ? -1 : 1;   // inward normal
