@@ -746,11 +746,11 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
     for (int j = 0; j < NPART; ++j) acc[j] = 0.0;
 
     // ring slot j holds plane z0 - 1 + j (mod 4).  The prologue stages the
-    // three planes the first node plane needs; each iteration issues the
-    // global loads of plane z+2 before its own work and writes them to the
-    // slot of plane z-2 (last read in the previous iteration) after it, so
-    // their latency overlaps the population traffic, and one barrier per
-    // plane orders the ring.
+    // three planes the first node plane needs; the global loads of plane z+2
+    // are issued during plane z-1 and written during plane z to the slot of
+    // plane z-2 (last read in the previous iteration), so their latency
+    // overlaps a plane of population traffic, and one barrier per plane
+    // orders the ring.
     stage(0, tl.z0 - 1);
     stage(1, tl.z0);
     stage(2, tl.z0 + 1);
@@ -768,6 +768,17 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
     int32_t ws_next = 0;
     if (active && (s_flag[1][c0] & LINKED)) lk_next = lnk[x + nx * y + nxy * tl.z0];
     if (active && (s_flag[1][c0] & F_NEAR_WALL)) ws_next = wsl_arr[x + nx * y + nxy * tl.z0];
+    // phi and flags of one plane for the ring, loaded a plane before they
+    // are written to LDS
+    T nv[NST];
+    uint8_t nf[NST];
+    auto fetch = [&](int zz) {
+        const int zo = (zz >= nz ? zz - nz : zz) * nxy;
+#pragma unroll
+        for (int j = 0; j < NST; ++j)
+            if (coff[j] >= 0) { nv[j] = phig[coff[j] + zo]; nf[j] = flg[coff[j] + zo]; }
+    };
+    if (tl.zn > 1) fetch(tl.z0 + 2);
     for (int k = 0; k < tl.zn; ++k) {
         const int z = tl.z0 + k;
         const bool more = k + 1 < tl.zn;
@@ -777,19 +788,10 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
         const uint32_t links = lk_next;
         const int32_t wslot_cur = ws_next;
         asm volatile("" ::"v"(links), "v"(wslot_cur));
-        T nv[NST];
-        uint8_t nf[NST];
-        if (more) {
-            const int zq = z + 2 >= nz ? z + 2 - nz : z + 2;
-            const int zo = zq * nxy;
-#pragma unroll
-            for (int j = 0; j < NST; ++j)
-                if (coff[j] >= 0) { nv[j] = phig[coff[j] + zo]; nf[j] = flg[coff[j] + zo]; }
-        }
-        // the staged plane goes to the free ring slot (k + 3) & 3 as soon as
-        // the node's populations have arrived (then the loads issued before
-        // them have too), before the node's stores: a wait for the plane
-        // after the stores would also wait for every store
+        // plane z + 2 (loaded during the previous plane) goes to the free
+        // ring slot (k + 3) & 3 as soon as the node's populations have
+        // arrived, before the node's stores (a wait for it after the stores
+        // would also wait for every store); the loads of plane z + 3 follow
         bool staged = !more;
         auto stage_next = [&]() {
             if (staged) return;
@@ -798,6 +800,7 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
             for (int j = 0; j < NST; ++j)
                 if (coff[j] >= 0) { s_phi[m][tid + j * NTHREADS] = nv[j]; s_flag[m][tid + j * NTHREADS] = nf[j]; }
             staged = true;
+            if (k + 2 < tl.zn) fetch(z + 3);
         };
         lk_next = 0u;
         ws_next = 0;
