@@ -569,15 +569,25 @@ def test_subvoxel_restore_fp64():
         assert np.array_equal(pa, pd)
 
 
-@pytest.mark.parametrize("storage", ["fp32_shift", "fp16_shift_g"])
-def test_subvoxel_reduced_precision(storage):
+@pytest.mark.parametrize("storage,shape", [
+    ("fp32_shift", (40, 12, 10)),
+    ("fp16_shift_g", (40, 12, 10)),
+    # the obstacle one node above the z = 0 layer leaves a one-node gap: the
+    # node between them has both links of the z pair solid
+    ("fp32_shift", (33, 40, 5)),
+])
+def test_subvoxel_reduced_precision(storage, shape):
     """FP32 arithmetic at sub-voxel walls, mobility correction off (R24 is
     about the correction, not the walls): phi, h within 1e-5 (FP32) and
     phi 1e-3 (FP16 g) after 40 steps."""
     import dataclasses
     from paper_2512_01032_amd import inputs
-    wl = inputs.random_small(40, 12, 10, seed=6, walls=True, open_x=True, subvoxel=True,
+    wl = inputs.random_small(*shape, seed=6, walls=True, open_x=True, subvoxel=True,
                              optimised_model=True, u_amp=0.002)
+    if shape == (33, 40, 5):
+        # the case must hold a pair with both links solid
+        s = wl.solid
+        assert (s[1:-1][(s[:-2] > 0) & (s[2:] > 0) & (s[1:-1] == 0)]).size > 0
     wl.phys = dataclasses.replace(wl.phys, mobility_corr=False)
     g, o = _run_pair(wl, 40, storage)
     err = compare_state(g, o, o.kinds())
