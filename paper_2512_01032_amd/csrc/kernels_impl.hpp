@@ -865,8 +865,8 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
         const int64_t wsl = wslot_cur, wstr = DC->n_wall;
         if (SV && MODE == MODE_STEP && solid && svx) {
             wtab = unip((const T*)DC->wall);
-            // Even steps load the wall fractions at the write-back.  Odd
-            // steps (fewer registers to spare) keep the fraction of a pair
+            // Even steps load the wall fractions into registers right after
+            // the stream step.  Odd steps (fewer registers to spare) keep the fraction of a pair
             // (i, ibar) with one solid link in the LDS slot of its fluid
             // partner until the write-back (the solid link's own slot takes
             // f_i^in); pairs with both links solid reload theirs there.
@@ -1073,7 +1073,8 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
         // (m: moving-wall term), and stored where the half-way rule puts g*_i
         const bool svw = SV && MODE == MODE_STEP && svx && solid;
         constexpr bool QREG = PAR == 0;   // fractions in registers
-        // the memory-to-LDS copies are counted by vmcnt only
+        // the compiler places no wait for the memory-to-LDS copies before
+        // the LDS reads below; the copies count in vmcnt
         if (PAR == 1 && sizeof(T) == 4 && svw) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         auto bb_value = [&](int i, T q, T gi, T gibar) -> T {
             const T m = slip ? mwall(i) : T(0);
