@@ -139,9 +139,14 @@ int choose_tz(const lbm_params* p, int tx) {
     const int64_t cols = (int64_t)((p->nx + tx - 1) / tx) * ((p->ny + ty - 1) / ty);
     // Short z-chunks: a tile's set-up (three staged phi planes) is cheap, and
     // many more tiles than resident blocks (4 per CU x 256 CUs) leave no
-    // half-empty last round.  8 planes, halved down to 2 until the lattice has
-    // >= 4096 tiles.
-    int tz = 8;
+    // half-empty last round.  2 planes with 4- and 8-byte g populations, 4
+    // with 2-byte ones, whose cheaper planes amortise the set-up over more
+    // (256 x 256 x 512 duct: FP32 18.35 / 18.72 / 18.86 G fluid updates/s
+    // at 8 / 4 / 2 planes, FP16 g 25.33 / 25.33 / 24.47, FP64 9.42 / 9.52 /
+    // 9.54); halved down to 2 until the lattice has >= 4096 tiles.
+    int sh, sg, sphi;
+    storage_sizes(p->storage, &sh, &sg, &sphi);
+    int tz = sg == 2 ? 4 : 2;
     while (tz > 2 && cols * ((p->nz + tz - 1) / tz) < 4096) tz /= 2;
     return std::min(tz, p->nz);
 }
