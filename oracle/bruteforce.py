@@ -72,6 +72,7 @@ class BruteForce:
         # sub-voxel walls: link fractions q[i] (where x + c_i is solid) and
         # normals from the signed distance, for fluid nodes with a solid link
         self.q = None
+        self.same_step = bool(getattr(wl, "meta", {}).get("subvoxel_same_step", False))
         sdf = getattr(wl, "sdf", None)
         if sdf is not None:
             near = np.zeros(shape, bool)
@@ -317,10 +318,17 @@ class BruteForce:
             else:
                 # interpolated bounce-back with the wall at fraction q of the
                 # link io; below 1/2 the upstream population is this step's
-                # incoming g_io
+                # incoming g_io, or (same_step) the post-collision g_io one
+                # node upstream, with the half-way value where that node is solid
                 q = self.q[io]
                 hi = gs[io] / (2 * q) + (1 - 1 / (2 * q)) * gs[i] - corr / (2 * q)
-                lo = 2 * q * gs[io] + (1 - 2 * q) * self.g[io] - corr
+                if self.same_step:
+                    up = shifted(gs[io], C[i], +1)
+                    up_solid = shifted(self.solid, C[i], +1)
+                    lo = np.where(up_solid, gs[io] - corr,
+                                  2 * q * gs[io] + (1 - 2 * q) * up - corr)
+                else:
+                    lo = 2 * q * gs[io] + (1 - 2 * q) * self.g[io] - corr
                 bb = np.where(q >= 0.5, hi, lo)
             gn[i] = np.where(src_solid, bb, shifted(gs[i], C[i], -1))
             if i < QP:

@@ -615,15 +615,25 @@ static void one_step(lbmref_state *s) {
                      * Lallemand 2001) with the wall at fraction q of the link.
                      * q >= 1/2: between g*_io(y) and g*_i(y); the moving-wall
                      * term scales by 1/(2q).  q < 1/2: between g*_io(y) and the
-                     * population g*_io(y - c_io) one link upstream, taken as the
-                     * one that arrived at y along io at this step (its value a
-                     * step earlier: exact for a steady flow, and local) */
+                     * population g*_io(y - c_io) one link upstream.  Default:
+                     * the one that arrived at y along io at this step stands in
+                     * for it (its value a step earlier: exact for a steady
+                     * flow, and local).  subvoxel_same_step: the upstream
+                     * node's value of this step, or the half-way rule where
+                     * that node is solid. */
                     double q = s->qw[19 * y + io];
-                    if (q >= 0.5)
+                    if (q >= 0.5) {
                         gv = gA[19 * y + io] / (2.0 * q) + (1.0 - 1.0 / (2.0 * q)) * gA[19 * y + i] -
                              mw / (2.0 * q);
-                    else
+                    } else if (p->subvoxel_same_step) {
+                        long up = neighbour(s, y, i, +1);
+                        if (s->kind[up] == K_SOLID)
+                            gv = gA[19 * y + io] - mw;
+                        else
+                            gv = 2.0 * q * gA[19 * y + io] + (1.0 - 2.0 * q) * gA[19 * up + io] - mw;
+                    } else {
                         gv = 2.0 * q * gA[19 * y + io] + (1.0 - 2.0 * q) * s->gpre[19 * y + io] - mw;
+                    }
                 }
                 if (i < Qh) hB[(long)Qh * y + i] = hA[(long)Qh * y + io];
             } else {

@@ -63,6 +63,14 @@ typedef struct lbmref_params {
     /* phase-field lattice: 7 (D3Q7, T = 1/4) or 19 (D3Q19, T = 1/3, as the
      * paper writes Eqs. 1-4); 0 means 7 */
     int q_phase;
+    /* sub-voxel walls, links whose wall lies nearer than half a link (q < 1/2):
+     * which upstream value the linear interpolated bounce-back takes.
+     * 0: the population that entered the node along the link at this step
+     *    (the upstream node's post-collision value of the step before; the
+     *    local form an in-place update can evaluate);
+     * 1: the upstream node's post-collision value of the same step (the
+     *    scheme as published); where that node is solid, the half-way rule. */
+    int subvoxel_same_step;
 } lbmref_params;
 
 typedef struct lbmref_diag {

@@ -51,6 +51,7 @@ class Params(ctypes.Structure):
         ("clamp_a", ctypes.c_double),
         ("hysteresis", ctypes.c_int), ("hyst_beta", ctypes.c_double),
         ("q_phase", ctypes.c_int),
+        ("subvoxel_same_step", ctypes.c_int),
     ]
 
 
@@ -127,6 +128,7 @@ def make_params(wl, clamp_a=1e-12):
     p.hysteresis = int(getattr(ph, "hysteresis", False))
     p.hyst_beta = getattr(ph, "hyst_beta", 0.0)
     p.q_phase = int(getattr(ph, "q_phase", 7))
+    p.subvoxel_same_step = int(getattr(wl, "meta", {}).get("subvoxel_same_step", False))
     return p
 
 
