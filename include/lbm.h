@@ -59,7 +59,11 @@ enum lbm_storage {
     LBM_FP32 = 1,           /* plain floats */
     LBM_FP32_SHIFT = 2,     /* floats holding f_i - w_i f_ref */
     LBM_FP16_SHIFT_G = 3,   /* h as shifted floats, g as scaled shifted halves */
-    LBM_FP16_SHIFT_ALL = 4  /* h and g as scaled shifted halves */
+    LBM_FP16_SHIFT_ALL = 4  /* h and g as scaled shifted halves: rejected (LBM_E_INVAL).
+                               phi = sum h_i carries the rounding of 11-bit h deviations
+                               (~1e-4 per step), which the counter-term of Eqs. 2-4 and
+                               the mobility correction of Eq. 5 amplify to phi errors of
+                               ~1e-1: no error bound can be stated for it */
 };
 
 enum lbm_face_bc { LBM_BC_PERIODIC = 0, LBM_BC_PRESSURE = 1 };
@@ -89,7 +93,7 @@ typedef struct lbm_params {
     double face_ramp[6];
     int32_t diag_every;     /* >0: FP64 diagnostics and the stability check every k steps */
     double u_max;           /* stability limit on |u| (<= 0: NaN check only) */
-    int32_t fp16_log2_scale_h; /* FP16 storage scale 2^k of h deviations (0: default) */
+    int32_t fp16_log2_scale_h; /* unused (h is never stored in FP16); kept for the layout */
     int32_t fp16_log2_scale_g; /* FP16 storage scale 2^k of g deviations (0: default) */
     int32_t hysteresis;     /* contact-angle hysteresis of the optimised model (Sec. III.A):
                                each wall link uses hyst_beta * (a value kept from the
@@ -190,9 +194,14 @@ int lbm_create(const lbm_params *p, const lbm_geometry *geo, const lbm_init *ini
 
 /* Queue nsteps time steps on the handle's stream and return.  Each step is
  * the phi pass, the wall pass (wetting values and stencil sums of the
- * near-wall nodes, Sec. II.B) and the fused stream-collide sweep.  Returns
- * LBM_E_UNSTABLE if a diagnostic taken before this call flagged NaN or
- * |u| > u_max (sticky). */
+ * near-wall nodes, Sec. II.B), the fused stream-collide sweep (Sec. II.A,
+ * Eqs. 1-16), the pressure-face ghosts (Sec. III.A) and the step counter.
+ * The steps are replayed from HIP graphs captured at the first call (one
+ * step per AA parity and diagnostic kind, and 16-step runs without a
+ * diagnostic step); while timing is on (lbm_set_timing) every kernel is
+ * launched on its own between events instead.  Both give bitwise the same
+ * state.  Returns LBM_E_UNSTABLE if a diagnostic taken before this call
+ * flagged NaN or |u| > u_max (sticky). */
 int lbm_step(lbm_handle *h, int64_t nsteps);
 
 /* Wait for queued work. */
@@ -210,6 +219,8 @@ int64_t lbm_step_count(const lbm_handle *h);
  * phi[N], P[N], u[3][N]: macroscopic fields of the current step, evaluated
  * from the populations entering its collision (after the text of Eq. 15).
  * Solid nodes read 0; ghosts read the owner's phi, the face pressure and 0.
+ * Allocates device staging for the requested fields for the duration of the
+ * call (LBM_E_DEVICE if that fails).
  * pops: h[q_phase][N] (if LBM_POP_H) then g[19][N] (if LBM_POP_G), decoded to double,
  * the value f_i(x) entering the collision; 0 at solid and ghost nodes. */
 int lbm_read_fields(lbm_handle *h, uint32_t mask, double *phi, double *P, double *u,

@@ -1,6 +1,7 @@
 // kernels.hip -- storage-mode dispatch of the kernel launchers.  The kernels
 // themselves live in kernels_impl.hpp; one translation unit per storage mode
-// (k_fp64, k_fp32, k_fp16g, k_fp16a) instantiates them.
+// (k_fp64, k_fp32, k_fp16g) instantiates them.  Storage with both h and g in
+// FP16 is rejected when a lattice is created and has no kernels.
 #include "pflbm.hpp"
 
 namespace pflbm {
@@ -14,6 +15,22 @@ __global__ void __launch_bounds__(NTHREADS) advance_kernel(Desc* __restrict__ de
     Desc* D = descs + k;
     const int64_t step = D->step;
     if (step < D->stop_step) D->step = step + 1;
+}
+
+// Zero n doubles: read-back staging, whose nodes in dropped all-solid tiles
+// no read kernel writes.  A kernel rather than a memset node, so the call is
+// safe inside a captured stream as well.
+__global__ void __launch_bounds__(NTHREADS) fill_zero_kernel(double* __restrict__ p, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * NTHREADS;
+    for (int64_t k = (int64_t)blockIdx.x * NTHREADS + threadIdx.x; k < n; k += stride) p[k] = 0.0;
+}
+
+hipError_t launch_fill_zero(double* p, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t want = (n + NTHREADS - 1) / NTHREADS;
+    const int blocks = (int)(want < 4096 ? want : 4096);
+    fill_zero_kernel<<<dim3(blocks), dim3(NTHREADS), 0, s>>>(p, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_advance(Desc* d, int nlat, hipStream_t s) {
@@ -34,10 +51,6 @@ hipError_t launch_sweep_fp16g(int, int, int, int, Desc*, const Tile*, int, int, 
 hipError_t launch_phi_fp16g(int, int, const Desc*, const Tile*, int, hipStream_t, int);
 hipError_t launch_restore_fp16g(int, int, const Desc*, const Tile*, int, const double*, hipStream_t);
 hipError_t launch_ghosts_fp16g(int, const Desc*, const GhostRef*, int, hipStream_t);
-hipError_t launch_sweep_fp16a(int, int, int, int, Desc*, const Tile*, int, int, ReadOut, InitIn, hipStream_t);
-hipError_t launch_phi_fp16a(int, int, const Desc*, const Tile*, int, hipStream_t, int);
-hipError_t launch_restore_fp16a(int, int, const Desc*, const Tile*, int, const double*, hipStream_t);
-hipError_t launch_ghosts_fp16a(int, const Desc*, const GhostRef*, int, hipStream_t);
 hipError_t launch_wall_fp64(int, const Desc*, const WallRef*, int, hipStream_t);
 hipError_t launch_wall_fp32(int, const Desc*, const WallRef*, int, hipStream_t);
 
@@ -55,7 +68,6 @@ hipError_t launch_sweep(int storage, int qp, int mode, int tx, int parity, Desc*
         case ST_FP32:
         case ST_FP32_SHIFT: return launch_sweep_fp32(qp, mode, tx, parity, d, tiles, ntiles, diag, ro, in, s);
         case ST_FP16_G: return launch_sweep_fp16g(qp, mode, tx, parity, d, tiles, ntiles, diag, ro, in, s);
-        case ST_FP16_ALL: return launch_sweep_fp16a(qp, mode, tx, parity, d, tiles, ntiles, diag, ro, in, s);
     }
     return hipErrorInvalidValue;
 }
@@ -67,7 +79,6 @@ hipError_t launch_phi(int storage, int qp, int parity, const Desc* d, const Tile
         case ST_FP32:
         case ST_FP32_SHIFT: return launch_phi_fp32(qp, parity, d, tiles, ntiles, s, force);
         case ST_FP16_G: return launch_phi_fp16g(qp, parity, d, tiles, ntiles, s, force);
-        case ST_FP16_ALL: return launch_phi_fp16a(qp, parity, d, tiles, ntiles, s, force);
     }
     return hipErrorInvalidValue;
 }
@@ -79,7 +90,6 @@ hipError_t launch_restore(int storage, int qp, int parity, const Desc* d, const 
         case ST_FP32:
         case ST_FP32_SHIFT: return launch_restore_fp32(qp, parity, d, tiles, ntiles, pops, s);
         case ST_FP16_G: return launch_restore_fp16g(qp, parity, d, tiles, ntiles, pops, s);
-        case ST_FP16_ALL: return launch_restore_fp16a(qp, parity, d, tiles, ntiles, pops, s);
     }
     return hipErrorInvalidValue;
 }
@@ -91,7 +101,6 @@ hipError_t launch_ghosts(int storage, int qp, const Desc* d, const GhostRef* gho
         case ST_FP32:
         case ST_FP32_SHIFT: return launch_ghosts_fp32(qp, d, ghosts, nghosts, s);
         case ST_FP16_G: return launch_ghosts_fp16g(qp, d, ghosts, nghosts, s);
-        case ST_FP16_ALL: return launch_ghosts_fp16a(qp, d, ghosts, nghosts, s);
     }
     return hipErrorInvalidValue;
 }

@@ -62,6 +62,15 @@ int validate_params(const lbm_params* p, const lbm_geometry* geo) {
     const int64_t N = (int64_t)p->nx * p->ny * p->nz;
     if (N >= ((int64_t)1 << 31)) { set_error("lattice of %lld nodes exceeds 2^31", (long long)N); return LBM_E_INVAL; }
     if (p->storage < ST_FP64 || p->storage > ST_FP16_ALL) { set_error("unknown storage mode %d", p->storage); return LBM_E_INVAL; }
+    if (p->storage == ST_FP16_ALL) {
+        // 11 significant bits on the h deviations leave phi = sum h_i with
+        // rounding noise of ~1e-4 per step, which the counter-term of Eqs. 2-4
+        // and the switches of Eq. 5 amplify to phi errors of ~1e-1: no stated
+        // bound holds, so the mode is not offered
+        set_error("storage LBM_FP16_SHIFT_ALL is not supported: FP16 phase-field populations "
+                  "give no bounded phi error; use LBM_FP16_SHIFT_G");
+        return LBM_E_INVAL;
+    }
     if (p->q_phase != 0 && p->q_phase != 7 && p->q_phase != 19) {
         set_error("q_phase %d: the phase lattice is D3Q7 (7) or D3Q19 (19)", p->q_phase);
         return LBM_E_INVAL;
@@ -461,7 +470,8 @@ void fill_desc(const lbm_params* p, const lbm_geometry* geo, const LatticeLayout
     d->gref = shifted ? p->P_ref * 3.0 : 0.0;
     const int ksh = p->fp16_log2_scale_h ? p->fp16_log2_scale_h : 3;
     const int ksg = p->fp16_log2_scale_g ? p->fp16_log2_scale_g : 10;
-    d->scale_h = p->storage == ST_FP16_ALL ? ldexp(1.0, ksh) : 1.0;
+    (void)ksh;                                   // h is never stored in FP16
+    d->scale_h = 1.0;
     d->scale_g = p->storage >= ST_FP16_G ? ldexp(1.0, ksg) : 1.0;
     d->u_max = p->u_max;
     // derived constants (Eq. 4 theta coefficient, Eq. 5 correction factor,
@@ -626,26 +636,41 @@ int upload_and_init(const lbm_params* p, const lbm_geometry* geo, const lbm_init
     return LBM_OK;
 }
 
-int read_lattice(int storage, const Desc& hdesc, int parity, Desc* d_desc, const Tile* d_tiles,
-                 int ntiles, const WallRef* d_walls, int nwalls, uint32_t mask, double* phi,
-                 double* P, double* u, double* pops, hipStream_t s) {
+// Doubles of device staging a read-back of this mask needs.
+size_t read_staging_elems(const Desc& hdesc, uint32_t mask, const double* phi, const double* P,
+                          const double* u, const double* pops) {
+    const size_t N = (size_t)hdesc.N;
+    const int qh = hdesc.q_phase == 19 ? 19 : 7;
+    size_t nd = 0;
+    if (phi && (mask & LBM_PHI)) nd += N;
+    if (P && (mask & LBM_P)) nd += N;
+    if (u && (mask & LBM_U)) nd += 3 * N;
+    // the read kernel writes every population row: all of them are staged
+    if (pops && (mask & (LBM_POP_H | LBM_POP_G))) nd += (size_t)(qh + QG) * N;
+    return nd;
+}
+
+int read_lattice_staged(int storage, const Desc& hdesc, int parity, Desc* d_desc, const Tile* d_tiles,
+                        int ntiles, const WallRef* d_walls, int nwalls, uint32_t mask, double* phi,
+                        double* P, double* u, double* pops, double* buf, hipStream_t s) {
     const int64_t N = hdesc.N;
     const bool want_pop = (mask & (LBM_POP_H | LBM_POP_G)) && pops;
-    double* buf = nullptr;
+    const int qh = hdesc.q_phase == 19 ? 19 : 7;
     size_t nd = 0;
     const size_t o_phi = nd; if (phi && (mask & LBM_PHI)) nd += N;
     const size_t o_P = nd; if (P && (mask & LBM_P)) nd += N;
     const size_t o_u = nd; if (u && (mask & LBM_U)) nd += 3 * N;
-    const int qh = hdesc.q_phase == 19 ? 19 : 7;
     const size_t o_pop = nd; if (want_pop) nd += (size_t)(qh + QG) * N;
-    if (nd) HIPCHK(hipMalloc(&buf, nd * sizeof(double)));
     ReadOut ro;
     ro.phi = (phi && (mask & LBM_PHI)) ? buf + o_phi : nullptr;
     ro.P = (P && (mask & LBM_P)) ? buf + o_P : nullptr;
     ro.u = (u && (mask & LBM_U)) ? buf + o_u : nullptr;
     ro.pops = want_pop ? buf + o_pop : nullptr;
     InitIn in = {nullptr, nullptr};
-    hipError_t e = launch_phi(storage, qh, parity, d_desc, d_tiles, ntiles, s, 1);
+    // nodes of dropped (all-solid) tiles are written by no read kernel: they
+    // read 0 from the cleared staging
+    hipError_t e = launch_fill_zero(buf, (int64_t)nd, s);
+    if (e == hipSuccess) e = launch_phi(storage, qh, parity, d_desc, d_tiles, ntiles, s, 1);
     if (e == hipSuccess) e = launch_wall(storage, MODE_READ, d_desc, d_walls, nwalls, s);
     if (e == hipSuccess) e = launch_sweep(storage, qh, MODE_READ, hdesc.tx, parity, d_desc, d_tiles, ntiles, 1, ro, in, s);
     if (e == hipSuccess && ro.phi) e = hipMemcpyAsync(phi, ro.phi, N * sizeof(double), hipMemcpyDeviceToHost, s);
@@ -662,9 +687,20 @@ int read_lattice(int storage, const Desc& hdesc, int parity, Desc* d_desc, const
                                hipMemcpyDeviceToHost, s);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (buf) hipFree(buf);
     if (e != hipSuccess) { set_error("read fields: %s", hipGetErrorString(e)); return LBM_E_DEVICE; }
     return LBM_OK;
+}
+
+int read_lattice(int storage, const Desc& hdesc, int parity, Desc* d_desc, const Tile* d_tiles,
+                 int ntiles, const WallRef* d_walls, int nwalls, uint32_t mask, double* phi,
+                 double* P, double* u, double* pops, hipStream_t s) {
+    const size_t nd = read_staging_elems(hdesc, mask, phi, P, u, pops);
+    double* buf = nullptr;
+    if (nd) HIPCHK(hipMalloc(&buf, nd * sizeof(double)));
+    const int rc = read_lattice_staged(storage, hdesc, parity, d_desc, d_tiles, ntiles, d_walls, nwalls,
+                                       mask, phi, P, u, pops, buf, s);
+    if (buf) hipFree(buf);
+    return rc;
 }
 
 }  // namespace pflbm

@@ -75,4 +75,14 @@ int read_lattice(int storage, const Desc& hdesc, int parity, Desc* d_desc, const
                  int ntiles, const WallRef* d_walls, int nwalls, uint32_t mask, double* phi,
                  double* P, double* u, double* pops, hipStream_t s);
 
+// Doubles of device staging read_lattice_staged needs for a mask (every
+// population row counts once pops is given with LBM_POP_H or LBM_POP_G).
+size_t read_staging_elems(const Desc& hdesc, uint32_t mask, const double* phi, const double* P,
+                          const double* u, const double* pops);
+// read_lattice with caller-provided device staging buf of at least
+// read_staging_elems() doubles: allocates nothing.  Synchronous.
+int read_lattice_staged(int storage, const Desc& hdesc, int parity, Desc* d_desc, const Tile* d_tiles,
+                        int ntiles, const WallRef* d_walls, int nwalls, uint32_t mask, double* phi,
+                        double* P, double* u, double* pops, double* buf, hipStream_t s);
+
 }  // namespace pflbm

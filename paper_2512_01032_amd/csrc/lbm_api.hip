@@ -7,40 +7,12 @@
 #include <vector>
 
 #include "../../include/lbm.h"
+#include "handle.hpp"
 #include "lattice_host.hpp"
 #include "pflbm.hpp"
 
 using namespace pflbm;
 
-struct lbm_handle {
-    lbm_params p;
-    lbm_geometry geo;
-    int device = 0;
-    hipStream_t stream = nullptr;
-    char* base = nullptr;        // device arena
-    bool own_arena = false;
-    LatticeLayout L;
-    Desc hdesc;                  // host copy of the descriptor at creation
-    Desc* ddesc = nullptr;
-    Tile* dtiles = nullptr;
-    int ntiles = 0;
-    GhostRef* dghosts = nullptr;
-    int nghosts = 0;
-    WallRef* dwalls = nullptr;   // near-wall fluid nodes (wall pass)
-    int nwalls = 0;
-    int64_t step = 0;            // steps queued so far
-    // stability flag copied back asynchronously after each lbm_step
-    int* h_unstable = nullptr;   // pinned
-    hipEvent_t unstable_ev = nullptr;
-    bool unstable_pending = false;
-    bool unstable = false;
-    // per-kernel timing
-    bool timing = false;
-    std::vector<hipEvent_t> ev_pool;
-    size_t ev_used = 0;
-    double phi_ms = 0.0, sweep_ms = 0.0;
-    int64_t steps_timed = 0;
-};
 
 #define HIPRET(expr)                                                              \
     do {                                                                          \
@@ -55,6 +27,12 @@ extern "C" size_t lbm_footprint(const lbm_params* p) { return footprint_bytes(p)
 
 static void free_handle(lbm_handle* h) {
     if (!h) return;
+    for (int a = 0; a < 2; ++a) {
+        for (int b = 0; b < 2; ++b)
+            if (h->one[a][b]) hipGraphExecDestroy(h->one[a][b]);
+        if (h->chunk[a]) hipGraphExecDestroy(h->chunk[a]);
+    }
+    if (h->cap_stream) hipStreamDestroy(h->cap_stream);
     if (h->base && h->own_arena) hipFree(h->base);
     if (h->h_unstable) hipHostFree(h->h_unstable);
     if (h->unstable_ev) hipEventDestroy(h->unstable_ev);
@@ -150,38 +128,121 @@ static int poll_unstable(lbm_handle* h, bool wait) {
     return LBM_OK;
 }
 
+static bool diag_step(const lbm_handle* h, int64_t t) {
+    const int64_t de = h->p.diag_every > 0 ? h->p.diag_every : 0;
+    return de > 0 && (t % de) == 0;
+}
+
+// Queue the kernels of steps t0 .. t0+n-1 on stream s: per step the phi pass,
+// the wall pass, the sweep (its AA parity and diagnostic instance chosen by
+// the step), the pressure ghosts and the step counter.  With events (timed
+// runs) the phi + wall passes and the sweep + ghosts + counter are bracketed.
+static int enqueue_steps(lbm_handle* h, int64_t t0, int64_t n, hipStream_t s, bool events) {
+    const int storage = h->p.storage;
+    const int qp = phase_q(&h->p);
+    const ReadOut ro = {nullptr, nullptr, nullptr, nullptr};
+    const InitIn in = {nullptr, nullptr};
+    for (int64_t k = 0; k < n; ++k) {
+        const int64_t t = t0 + k;
+        const int diag = diag_step(h, t) ? 1 : 0;
+        hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
+        if (events) {
+            e0 = next_event(h); e1 = next_event(h); e2 = next_event(h);
+            if (!e0 || !e1 || !e2) { set_error("event pool"); return LBM_E_DEVICE; }
+            HIPRET(hipEventRecord(e0, s));
+        }
+        const int par = (int)(t & 1);
+        HIPRET(launch_phi(storage, qp, par, h->ddesc, h->dtiles, h->ntiles, s));
+        if (h->nwalls) HIPRET(launch_wall(storage, MODE_STEP, h->ddesc, h->dwalls, h->nwalls, s));
+        if (events) HIPRET(hipEventRecord(e1, s));
+        HIPRET(launch_sweep(storage, qp, h->p.subvoxel ? MODE_STEP_SV : MODE_STEP, h->L.tx, par, h->ddesc,
+                            h->dtiles, h->ntiles, diag, ro, in, s));
+        if (h->nghosts) HIPRET(launch_ghosts(storage, qp, h->ddesc, h->dghosts, h->nghosts, s));
+        HIPRET(launch_advance(h->ddesc, 1, s));
+        if (events) HIPRET(hipEventRecord(e2, s));
+    }
+    return LBM_OK;
+}
+
+// Capture n steps starting at parity par (diagnostic step or not for a single
+// step) into an executable graph.  The kernels read the step, and with it
+// the face pressures, from the descriptor, so the graph replays at any step
+// of that parity and diagnostic kind.
+static int capture_steps(lbm_handle* h, int par, int diag, int64_t n, hipGraphExec_t* out) {
+    // a representative step of the wanted kind: the first step >= 2 with the
+    // parity par that is (or is not) a diagnostic step
+    const int64_t de = h->p.diag_every > 0 ? h->p.diag_every : 0;
+    int64_t t0 = -1;
+    if (diag) {
+        for (int64_t m = 1; m <= 2 && t0 < 0; ++m)
+            if (((de * m) & 1) == par) t0 = de * m;
+    } else {
+        for (int64_t t = 2 + par; t < 2 + 2 * (de + 2) + 2 * n && t0 < 0; t += 2) {
+            bool any = false;
+            for (int64_t k = 0; k < n; ++k) any |= diag_step(h, t + k);
+            if (!any) t0 = t;
+        }
+    }
+    if (t0 < 0) { *out = nullptr; return LBM_OK; }   // no step of this kind exists
+    hipGraph_t g = nullptr;
+    HIPRET(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    const int rc = enqueue_steps(h, t0, n, h->cap_stream, false);
+    const hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+    if (rc != LBM_OK) { if (g) hipGraphDestroy(g); return rc; }
+    if (e != hipSuccess) { set_error("hipStreamEndCapture: %s", hipGetErrorString(e)); return LBM_E_DEVICE; }
+    const hipError_t e2 = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e2 != hipSuccess) { set_error("hipGraphInstantiate: %s", hipGetErrorString(e2)); return LBM_E_DEVICE; }
+    return LBM_OK;
+}
+
+static int ensure_graphs(lbm_handle* h) {
+    if (h->graphs_ready) return LBM_OK;
+    if (!h->cap_stream) HIPRET(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    for (int par = 0; par < 2; ++par) {
+        for (int diag = 0; diag < 2; ++diag) {
+            if (diag && h->p.diag_every <= 0) continue;
+            int rc = capture_steps(h, par, diag, 1, &h->one[par][diag]);
+            if (rc != LBM_OK) return rc;
+        }
+        int rc = capture_steps(h, par, 0, GRAPH_CHUNK, &h->chunk[par]);
+        if (rc != LBM_OK) return rc;
+    }
+    h->graphs_ready = true;
+    return LBM_OK;
+}
+
 extern "C" int lbm_step(lbm_handle* h, int64_t nsteps) {
     if (!h) { set_error("handle is NULL"); return LBM_E_INVAL; }
     if (nsteps < 0) { set_error("nsteps < 0"); return LBM_E_INVAL; }
     int rc = poll_unstable(h, false);
     if (rc != LBM_OK) return rc;
+    if (nsteps == 0) return LBM_OK;
     HIPRET(hipSetDevice(h->device));
-    const int storage = h->p.storage;
-    const int qp = phase_q(&h->p);
-    const ReadOut ro = {nullptr, nullptr, nullptr, nullptr};
-    const InitIn in = {nullptr, nullptr};
     const int64_t de = h->p.diag_every > 0 ? h->p.diag_every : 0;
     bool any_diag = false;
-    for (int64_t k = 0; k < nsteps; ++k) {
-        const int64_t t = h->step + k;
-        const int diag = de > 0 && (t % de) == 0;
-        any_diag |= (diag != 0);
-        hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
-        if (h->timing) {
-            e0 = next_event(h); e1 = next_event(h); e2 = next_event(h);
-            if (!e0 || !e1 || !e2) { set_error("event pool"); return LBM_E_DEVICE; }
-            HIPRET(hipEventRecord(e0, h->stream));
+    for (int64_t k = 0; k < nsteps && !any_diag; ++k) any_diag = diag_step(h, h->step + k);
+    if (h->timing) {
+        // timed runs launch each kernel on its own, bracketed by events
+        rc = enqueue_steps(h, h->step, nsteps, h->stream, true);
+        if (rc != LBM_OK) return rc;
+    } else {
+        rc = ensure_graphs(h);
+        if (rc != LBM_OK) return rc;
+        int64_t k = 0;
+        while (k < nsteps) {
+            const int64_t t = h->step + k;
+            const int par = (int)(t & 1);
+            bool chunk_ok = h->chunk[par] && nsteps - k >= GRAPH_CHUNK;
+            if (chunk_ok && de > 0) {
+                const int64_t next_diag = ((t + de - 1) / de) * de;
+                chunk_ok = next_diag >= t + GRAPH_CHUNK;
+            }
+            hipGraphExec_t g = chunk_ok ? h->chunk[par] : h->one[par][diag_step(h, t) ? 1 : 0];
+            if (!g) { set_error("no step graph for step %lld", (long long)t); return LBM_E_STATE; }
+            HIPRET(hipGraphLaunch(g, h->stream));
+            k += chunk_ok ? GRAPH_CHUNK : 1;
         }
-        const int par = (int)(t & 1);
-        HIPRET(launch_phi(storage, qp, par, h->ddesc, h->dtiles, h->ntiles, h->stream));
-        if (h->nwalls) HIPRET(launch_wall(storage, MODE_STEP, h->ddesc, h->dwalls, h->nwalls, h->stream));
-        if (h->timing) HIPRET(hipEventRecord(e1, h->stream));
-        HIPRET(launch_sweep(storage, qp, h->p.subvoxel ? MODE_STEP_SV : MODE_STEP, h->L.tx, par, h->ddesc, h->dtiles, h->ntiles, diag, ro, in,
-                            h->stream));
-        if (h->nghosts)
-            HIPRET(launch_ghosts(storage, qp, h->ddesc, h->dghosts, h->nghosts, h->stream));
-        HIPRET(launch_advance(h->ddesc, 1, h->stream));
-        if (h->timing) HIPRET(hipEventRecord(e2, h->stream));
     }
     h->step += nsteps;
     if (any_diag && !h->unstable_pending) {

@@ -491,8 +491,9 @@ extern "C" int lbm_server_create(const lbm_server_cfg* cfg, lbm_server** out) {
     if (!out || !cfg) { set_error("NULL argument"); return LBM_E_INVAL; }
     *out = nullptr;
     if (cfg->max_slots < 0 || cfg->max_slots > 256) { set_error("max_slots must be in [0, 256]"); return LBM_E_INVAL; }
-    if (cfg->storage < LBM_FP64 || cfg->storage > LBM_FP16_SHIFT_ALL) {
-        set_error("unknown storage mode %d", cfg->storage);
+    if (cfg->storage < LBM_FP64 || cfg->storage >= LBM_FP16_SHIFT_ALL) {
+        set_error(cfg->storage == LBM_FP16_SHIFT_ALL ? "storage LBM_FP16_SHIFT_ALL is not supported"
+                                                     : "unknown storage mode %d", cfg->storage);
         return LBM_E_INVAL;
     }
     if (cfg->ticks_per_sync < 0) { set_error("ticks_per_sync < 0"); return LBM_E_INVAL; }

@@ -73,7 +73,8 @@ int main(void) {
 
 
 @pytest.mark.parametrize("field,value", [("nu_l", 0.0), ("W", -1.0), ("rho_g", 0.0), ("nx", 0),
-                                         ("storage", 9), ("q_phase", 8), ("hysteresis", 3),
+                                         ("storage", 9), ("storage", 4), ("q_phase", 8),
+                                         ("hysteresis", 3),
                                          ("hysteresis", -1), ("subvoxel", 2)])
 def test_invalid_parameters_rejected_on_host(field, value):
     from paper_2512_01032_amd import inputs, lbm
@@ -193,3 +194,19 @@ def test_population_layout_limits():
     # FP16 g: 66 bytes per node in one group
     assert fp(256, 256, 992, "fp16_shift_g") > 0
     assert fp(256, 256, 993, "fp16_shift_g") == 0
+
+
+def test_fp16_phase_storage_rejected_on_host():
+    """Storage with the phase-field populations in FP16 (LBM_FP16_SHIFT_ALL)
+    has no bounded phi error and is refused by lbm_create, lbm_footprint and
+    the server, before any device call."""
+    from paper_2512_01032_amd import inputs, lbm
+    wl = inputs.random_small(8, 6, 5, seed=0)
+    assert lbm.footprint(wl, "fp16_shift_all") == 0
+    with pytest.raises(lbm.LbmError) as ei:
+        lbm.Lattice(wl, storage="fp16_shift_all")
+    assert ei.value.code == lbm.LBM_E_INVAL
+    assert b"FP16_SHIFT_ALL" in lbm.lbm_last_error()
+    with pytest.raises(lbm.LbmError) as ei:
+        lbm.Server(storage="fp16_shift_all")
+    assert ei.value.code == lbm.LBM_E_INVAL

@@ -17,7 +17,10 @@ Tolerances (max |gpu - oracle| / max |oracle| per field over fluid nodes):
   to 3e-8 absolute, which is 1e-5 in u in the gas: its velocity error is
   reported, not bounded (the reason the shifted storage exists).
 * FP16 storage of g (h in FP32): phi within 1e-3 after 50 steps on walls and
-  pressure faces.  FP16 storage of h as well: reported only (see DESIGN).
+  pressure faces.  FP16 storage of h as well is rejected by lbm_create.
+* With the mobility correction of Eq. 5 on, reduced-precision storage is
+  held to a bound set by the oracle's own sensitivity to noise of the
+  storage's size on the same input (test_d3q19_phase_reduced_precision).
 """
 from __future__ import annotations
 
@@ -128,6 +131,32 @@ def test_restore_and_determinism_fp64():
     assert np.array_equal(hd, ha) and np.array_equal(gd, ga)
 
 
+@pytest.mark.parametrize("diag_every", [0, 7])
+def test_graph_replay_equals_eager_launches(diag_every):
+    """lbm_step replays captured graphs (single steps by parity and
+    diagnostic kind, and 16-step chunks); with timing on it launches every
+    kernel on its own.  Both give bitwise the same state over 45 steps
+    taken in uneven calls (chunks, single steps and diagnostic steps mixed),
+    with reads between the calls, and the same diagnostics."""
+    from paper_2512_01032_amd import inputs
+    lbm = _lbm()
+    wl = inputs.random_small(40, 12, 10, seed=8, walls=True, open_x=True,
+                             optimised_model=True, u_amp=0.002)
+    a = lbm.Lattice(wl, storage="fp32_shift", diag_every=diag_every, u_max=0.5)
+    b = lbm.Lattice(wl, storage="fp32_shift", diag_every=diag_every, u_max=0.5)
+    b.set_timing(True)
+    for n in (1, 17, 3, 16, 8):
+        a.step(n)
+        b.step(n)
+        ha, ga = a.pops()
+        hb, gb = b.pops()
+        assert a.t == b.t
+        assert np.array_equal(ha, hb) and np.array_equal(ga, gb), n
+    da, db = a.diagnostics(), b.diagnostics()
+    assert da == db
+    b.get_timing()
+
+
 def test_translating_droplet_fp64():
     """A droplet carried by a uniform flow: momentum is O(1e-2) and is held to
     1e-10 relative to its maximum."""
@@ -155,7 +184,7 @@ def test_c1_fp32_modes(storage):
         assert err["P"] <= 1e-3 and err["mom"] <= 1e-3, err
 
 
-@pytest.mark.parametrize("storage", ["fp32_shift", "fp16_shift_g", "fp16_shift_all"])
+@pytest.mark.parametrize("storage", ["fp32_shift", "fp16_shift_g"])
 def test_walls_open_faces_reduced_precision(storage):
     """Reduced-precision storage on walls + pressure faces (module docstring)."""
     from paper_2512_01032_amd import inputs
@@ -165,8 +194,6 @@ def test_walls_open_faces_reduced_precision(storage):
     err = compare_state(g, o, o.kinds())
     print(storage, err, flush=True)
     assert all(np.isfinite(v) for v in err.values()), err
-    if storage == "fp16_shift_all":
-        return   # reported only
     bound = {"fp32_shift": 1e-5, "fp16_shift_g": 1e-3}[storage]
     assert err["phi"] <= bound, err
 
@@ -211,10 +238,13 @@ def _full(name):
             "duct": inputs.constricted_duct}[name]()
 
 
-_DUCT_STEPS = 3
+# The timed duct: slug ends a quarter cell off the nodes (see
+# test_full_size_duct_fp64_first_step for why), 20 steps.
+_DUCT_STEPS = 20
+_DUCT_OFFSET = 0.25
 
 
-def _duct(slug_offset=0.0):
+def _duct(slug_offset=_DUCT_OFFSET):
     from paper_2512_01032_amd import inputs
     return inputs.constricted_duct(slug_offset=slug_offset)
 
@@ -227,11 +257,13 @@ def _snapshot(o):
 
 @pytest.fixture(scope="module")
 def duct_oracle():
-    """The constricted duct stepped by the oracle once for this module (its
-    FP64 state is 15 GB of host memory); the full state after 3 steps."""
+    """The benchmark's constricted duct stepped by the oracle once for this
+    module (its FP64 state is 15 GB of host memory); the full state after
+    _DUCT_STEPS steps."""
     from oracle import ref
     require_gpu()
     wl = _duct()
+    print("oracle: duct, slug offset %g, %d steps" % (_DUCT_OFFSET, _DUCT_STEPS), flush=True)
     o = ref.Oracle(wl)
     o.step(_DUCT_STEPS)
     snap = _snapshot(o)
@@ -252,6 +284,8 @@ def _check_fp64_arrays(g, snap, kinds, name, tol=FP64_TOL):
     # sum of phi: the per-node bound, summed over the lattice
     dg, do = g.diagnostics(), snap["diag"]
     assert abs(dg["phi_sum"] - do["phi_sum"]) <= tol * abs(do["phi_sum"])
+    # solid nodes read 0, also those of the dropped all-solid tiles
+    assert not pg[kinds == 1].any() and not Pg[kinds == 1].any()
 
 
 def _check_fp64(g, o, name):
@@ -271,13 +305,36 @@ def test_full_size_fp64(name, steps):
 
 
 @pytest.mark.timeout(400)
-def test_full_size_duct_fp64_first_step(duct_oracle):
-    """The benchmark's duct in FP64: 1e-10 after the first step (against the
-    oracle's state after step 1, taken from a separate oracle run)."""
-    from oracle import ref
-    wl, kinds, snap3 = duct_oracle
+def test_full_size_duct_fp64(duct_oracle):
+    """The benchmark's duct (slug ends a quarter cell off the nodes) in
+    FP64: 1e-10 after 20 steps, in the launch configuration the benchmark
+    times."""
+    wl, kinds, snap = duct_oracle
     lbm = _lbm()
-    print("case duct fp64 step 1", flush=True)
+    print("case duct fp64 steps %d" % _DUCT_STEPS, flush=True)
+    g = lbm.Lattice(wl, storage="fp64")
+    g.step(_DUCT_STEPS)
+    _check_fp64_arrays(g, snap, kinds, "duct %d steps" % _DUCT_STEPS)
+    g.close()
+
+
+@pytest.mark.timeout(400)
+def test_full_size_duct_fp64_first_step(duct_oracle):
+    """The duct with its slug ends on the nodes, FP64, 1e-10 after the first
+    step.  With the slugs on the nodes the slugs' mid-planes and the
+    cross-section's diagonals are exact symmetry planes through nodes where
+    0 < phi < 1: there the normal grad/(|grad| + eps), the wall tangent
+    g_t/(|g_t| + eps) and the sign lap/(|lap| + eps) of the mobility
+    correction divide a vanishing quantity by |.| + 1e-10, so two correct
+    FP64 evaluations that sum symmetric terms in different orders part by
+    their rounding residue times 1e10 (2e-7 relative in phi after 3 steps).
+    Off the nodes (the benchmark's input) every such argument is O(1e-5) and
+    the two agree to rounding for as long as they are run."""
+    from oracle import ref
+    _, kinds, _ = duct_oracle
+    lbm = _lbm()
+    wl = _duct(slug_offset=0.0)
+    print("case duct fp64 slugs on nodes, step 1", flush=True)
     o = ref.Oracle(wl)
     o.step(1)
     snap = _snapshot(o)
@@ -288,38 +345,11 @@ def test_full_size_duct_fp64_first_step(duct_oracle):
     g.close()
 
 
-@pytest.mark.timeout(400)
-def test_full_size_duct_fp64_offset_slugs():
-    """FP64 duct with the slug ends a quarter cell off the nodes, 1e-10 after
-    3 steps.  With the slugs on the nodes (the benchmark input) the slugs'
-    mid-planes and the cross-section's diagonals are exact symmetry planes
-    through nodes where 0 < phi < 1: there the normal grad/(|grad| + eps),
-    the wall tangent g_t/(|g_t| + eps) and the sign lap/(|lap| + eps) of the
-    mobility correction divide a vanishing quantity by |.| + 1e-10, so two
-    correct FP64 evaluations that sum symmetric terms in different orders
-    part by their rounding residue times 1e10 (2e-7 relative in phi after 3
-    steps).  Off the nodes every such argument is O(1e-5) and the two agree
-    to rounding."""
-    from oracle import ref
-    lbm = _lbm()
-    wl = _duct(slug_offset=0.25)
-    print("case duct fp64 offset slugs steps %d" % _DUCT_STEPS, flush=True)
-    o = ref.Oracle(wl)
-    o.step(_DUCT_STEPS)
-    snap = _snapshot(o)
-    kinds = o.kinds()
-    del o
-    g = lbm.Lattice(wl, storage="fp64")
-    g.step(_DUCT_STEPS)
-    _check_fp64_arrays(g, snap, kinds, "duct offset slugs")
-    g.close()
-
-
 @pytest.mark.timeout(300)
 @pytest.mark.parametrize("storage,bound", [("fp32_shift", 1e-4), ("fp16_shift_g", 1e-3)])
 def test_full_size_duct_reduced_precision(duct_oracle, storage, bound):
     """The benchmark workload in the benchmarked storage modes: max |phi -
-    oracle| after 3 steps."""
+    oracle| after 20 steps."""
     wl, kinds, snap = duct_oracle
     lbm = _lbm()
     print("case duct %s steps %d" % (storage, _DUCT_STEPS), flush=True)
@@ -467,6 +497,31 @@ def test_d3q19_phase_restore_with_hysteresis_fp64():
         assert err[k] <= FP64_TOL, (k, err[k])
 
 
+def _oracle_noise_spread(wl, steps, amplitude, seeds=(2, 3, 4)):
+    """How far the FP64 oracle itself moves phi on this input when every
+    step adds uniform noise of +-amplitude to the rest population h_0 of
+    every fluid node: max over a few noise seeds of max |phi_noisy - phi|.
+    The conditioning of the method on the input, which no evaluation in a
+    storage of that resolution can beat."""
+    from oracle import ref
+    clean = ref.Oracle(wl)
+    clean.step(steps)
+    pc = clean.fields()[0]
+    fluid = clean.kinds() == 0
+    worst = 0.0
+    for sd in seeds:
+        b = ref.Oracle(wl)
+        rng = np.random.default_rng(sd)
+        for t in range(steps):
+            h, gp = b.pops()
+            h = h.copy()
+            h[0] += np.where(fluid, amplitude * rng.uniform(-1.0, 1.0, h[0].shape), 0.0)
+            b.set_pops(h, gp, t)
+            b.step(1)
+        worst = max(worst, float(np.abs(b.fields()[0] - pc)[fluid].max()))
+    return worst
+
+
 @pytest.mark.parametrize("storage,mc,bound", [
     ("fp32_shift", False, 1e-5),
     ("fp32_shift", True, 1e-3),
@@ -476,44 +531,39 @@ def test_d3q19_phase_restore_with_hysteresis_fp64():
 def test_d3q19_phase_reduced_precision(storage, mc, bound):
     """FP32 arithmetic on the D3Q19 phase lattice, walls + pressure faces,
     optimised model, 40 steps.  Without the mobility correction FP32 shifted
-    storage holds phi and h to 1e-5.  With it, the phi error is set by the
-    method's conditioning, not by the lattice: Eq. 5 ramps over D = 1e-4
-    near phi = 0 and 1, so the ~3e-8 absolute resolution of phi in FP32
-    (0.5 + sum of shifted deviations) is amplified 1e4-fold; the FP64
-    oracle fed noise of that size every step moves by 1.9e-4 on this input
-    (the CPU test of that amplification is in the oracle pins).  Its sign
-    term lap / (|lap| + eps) also flips on rounding noise where the
-    Laplacian vanishes, a discrete event that moves phi by ~1e-2 around the
-    node: an input can sit on such a flip, and another rounding of the same
-    arithmetic lands on the other side (seen once with FP16 g, where phi
-    moves by 6e-2 on this input and by 2e-4 to 3e-4 when phi0 is perturbed
-    by 1e-9 to 1e-7).  With the correction on, the bound therefore holds
-    for the median of three copies of the input, each perturbed by 1e-9
-    (seeded, the same input on both sides)."""
+    storage holds phi and h to 1e-5 and FP16 g phi to 1e-3.  With it, the
+    phi error is set by the method's conditioning on the input, not by the
+    lattice: Eq. 5 ramps over D = 1e-4 near phi = 0 and 1, and its sign term
+    lap / (|lap| + eps) flips on rounding noise where the Laplacian
+    vanishes, a discrete event that moves phi by ~1e-2 around the node.
+    The bound is therefore max(bound, 3 S): S is how far the FP64 oracle
+    moves phi on this input when fed per-step phi noise of the storage's
+    size (3e-8, the resolution of phi = 1/2 + sum of shifted FP32 h, for
+    FP32; 1e-6 for FP16 g, whose velocity rounding (g deviations to 11
+    bits at scale 2^10) perturbs the h equilibria by about that much), the
+    worst of three noise seeds.  On this input S is 1.8e-4 (FP32) and
+    2.8e-2 (FP16 g: one noise seed lands on a sign flip), so the FP16 g
+    bound is 8e-2: a correct FP16 evaluation can be that far from the FP64
+    oracle here, as R24 records."""
     import dataclasses
     from paper_2512_01032_amd import inputs
-    base = _q19(inputs.random_small(40, 12, 10, seed=6, walls=True, open_x=True,
-                                    optimised_model=True, u_amp=0.002))
-    base.phys = dataclasses.replace(base.phys, mobility_corr=mc)
-    copies = [base]
+    wl = _q19(inputs.random_small(40, 12, 10, seed=6, walls=True, open_x=True,
+                                  optimised_model=True, u_amp=0.002))
+    wl.phys = dataclasses.replace(wl.phys, mobility_corr=mc)
+    g, o = _run_pair(wl, 40, storage)
+    err = compare_state(g, o, o.kinds())
+    g.close()
+    print(storage, "mobility correction", mc, err, flush=True)
+    assert all(np.isfinite(v) for v in err.values()), err
+    limit = bound
     if mc:
-        copies = []
-        for k in range(3):
-            wl = dataclasses.replace(base)
-            wl.phi0 = base.phi0 + 1e-9 * np.random.default_rng(100 + k).standard_normal(base.phi0.shape)
-            copies.append(wl)
-    errs = []
-    for wl in copies:
-        g, o = _run_pair(wl, 40, storage)
-        err = compare_state(g, o, o.kinds())
-        g.close()
-        print(storage, "mobility correction", mc, err, flush=True)
-        assert all(np.isfinite(v) for v in err.values()), err
-        errs.append(err)
-    assert float(np.median([e["phi"] for e in errs])) <= bound, errs
+        spread = _oracle_noise_spread(wl, 40, {"fp32_shift": 3e-8, "fp16_shift_g": 1e-6}[storage])
+        limit = max(bound, 3.0 * spread)
+        print("oracle noise spread", spread, "limit", limit, flush=True)
+    assert err["phi"] <= limit, (err, limit)
     if storage == "fp32_shift" and not mc:
         for k in ("h", "g", "P"):
-            assert errs[0][k] <= 1e-5, (k, errs[0])
+            assert err[k] <= 1e-5, (k, err)
 
 
 # ----------------------------------------------------------- sub-voxel walls
