@@ -226,6 +226,21 @@ int64_t lbm_step_count(const lbm_handle *h);
 int lbm_read_fields(lbm_handle *h, uint32_t mask, double *phi, double *P, double *u,
                     double *pops);
 
+/* lbm_read_fields for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same read-back and result, staged through one fixed array
+ * of LBM_NOALLOC_MAX_DOUBLES doubles (64 MiB) that the library holds on
+ * every GPU it runs on until the process ends, so the call allocates
+ * nothing.  The requested fields must fit it: N doubles each for phi and P,
+ * 3 N for u, (q_phase + 19) N for pops with LBM_POP_H or LBM_POP_G (all
+ * population rows are staged); larger requests return LBM_E_INVAL before
+ * any device work.  Every call on one GPU shares that array: calls that
+ * overlap on one GPU (from several threads, on any handles) race and must be
+ * serialised by the caller.  Synchronous. */
+#define LBM_NOALLOC_MAX_DOUBLES (8u << 20)
+int lbm_read_fields_noalloc(lbm_handle *h, uint32_t mask, double *phi, double *P, double *u,
+                            double *pops);
+
 /* FP64 reduction of the current state (Sigma phi, Sigma rho u, max |u|, mean
  * pressures).  Synchronous. */
 int lbm_reduce(lbm_handle *h, lbm_diag *d);

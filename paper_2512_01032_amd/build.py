@@ -19,7 +19,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "liblbm.so")
 
 SOURCES = ["k_fp64.hip", "k_fp32.hip", "k_fp16g.hip", "kernels.hip",
-           "lattice_host.hip", "lbm_api.hip", "serve.hip"]
+           "lattice_host.hip", "lbm_api.hip", "read_noalloc.hip", "serve.hip"]
 ARCH = os.environ.get("PFLBM_ARCH", "gfx950")
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -17,12 +17,13 @@ LIB_PATH = os.path.join(PKG, "liblbm.so")
 
 LBM_OK, LBM_PENDING = 0, 1
 LBM_E_INVAL, LBM_E_NOMEM, LBM_E_DEVICE, LBM_E_UNSTABLE, LBM_E_STATE = -1, -2, -3, -4, -5
+NOALLOC_MAX_DOUBLES = 8 << 20   # LBM_NOALLOC_MAX_DOUBLES
 STORAGE = {"fp64": 0, "fp32": 1, "fp32_shift": 2, "fp16_shift_g": 3, "fp16_shift_all": 4}
 LBM_PHI, LBM_P, LBM_U, LBM_POP_H, LBM_POP_G = 1, 2, 4, 8, 16
 LBM_INIT_FIELDS, LBM_INIT_POPULATIONS = 0, 1
 
 EXPORTED = ("lbm_footprint", "lbm_create", "lbm_step", "lbm_sync", "lbm_step_count",
-            "lbm_read_fields", "lbm_reduce", "lbm_set_timing", "lbm_get_timing", "lbm_destroy",
+            "lbm_read_fields", "lbm_read_fields_noalloc", "lbm_reduce", "lbm_set_timing", "lbm_get_timing", "lbm_destroy",
             "lbm_last_error", "lbm_get_info", "lbm_server_create", "lbm_submit", "lbm_poll",
             "lbm_server_drain", "lbm_server_clock", "lbm_result_free", "lbm_server_destroy")
 
@@ -114,6 +115,7 @@ def _load():
     L.lbm_step_count.restype = c_int64
     L.lbm_step_count.argtypes = [vp]
     L.lbm_read_fields.argtypes = [vp, ctypes.c_uint32, vp, vp, vp, vp]
+    L.lbm_read_fields_noalloc.argtypes = [vp, ctypes.c_uint32, vp, vp, vp, vp]
     L.lbm_reduce.argtypes = [vp, ctypes.POINTER(lbm_diag)]
     L.lbm_set_timing.argtypes = [vp, c_int32]
     L.lbm_get_timing.argtypes = [vp, ctypes.POINTER(c_double), ctypes.POINTER(c_double),
@@ -141,6 +143,7 @@ lbm_step = _L.lbm_step
 lbm_sync = _L.lbm_sync
 lbm_step_count = _L.lbm_step_count
 lbm_read_fields = _L.lbm_read_fields
+lbm_read_fields_noalloc = _L.lbm_read_fields_noalloc
 lbm_reduce = _L.lbm_reduce
 lbm_set_timing = _L.lbm_set_timing
 lbm_get_timing = _L.lbm_get_timing
@@ -267,6 +270,25 @@ class Lattice:
         check(lbm_read_fields(self.h, LBM_PHI | LBM_P | LBM_U, phi.ctypes.data, P.ctypes.data,
                               u.ctypes.data, None))
         return phi, P, u
+
+    def read(self, mask, noalloc=False):
+        """lbm_read_fields (or lbm_read_fields_noalloc) of the fields in mask:
+        a dict of the arrays asked for."""
+        qh = self.params.q_phase if self.params.q_phase else 7
+        out = {}
+        phi = np.zeros(self.shape) if mask & LBM_PHI else None
+        P = np.zeros(self.shape) if mask & LBM_P else None
+        u = np.zeros((3,) + self.shape) if mask & LBM_U else None
+        nq = (qh if mask & LBM_POP_H else 0) + (19 if mask & LBM_POP_G else 0)
+        pops = np.zeros((nq,) + self.shape) if nq else None
+        fn = lbm_read_fields_noalloc if noalloc else lbm_read_fields
+        check(fn(self.h, mask, None if phi is None else phi.ctypes.data,
+                 None if P is None else P.ctypes.data, None if u is None else u.ctypes.data,
+                 None if pops is None else pops.ctypes.data))
+        for k, v in (("phi", phi), ("P", P), ("u", u), ("pops", pops)):
+            if v is not None:
+                out[k] = v
+        return out
 
     def pops(self):
         qh = self.params.q_phase if self.params.q_phase else 7
