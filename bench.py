@@ -14,7 +14,13 @@ for the sweep kernel (the dominant one): algorithmic bytes = 2 (7 s_h +
 19 s_g) per fluid node (every population read once and written once) over
 the sweep's average duration measured with HIP events on its stream.  The
 CPU baseline is the FP64 oracle on the host cores, on a bounded sample: the
-same lattice for a few steps.
+same lattice for a few steps, median of three, on all cores and on one.
+The oracle legs (skipped with --no-cpu-baseline) also run the configured
+validation workloads at full size and length on the GPU: the sessile droplet
+(128 x 128 x 96, 20k steps: contact angle, Laplace pressure), the capillary
+filling (1024 x 32 x 32, 50k steps: meniscus position against Washburn) and
+the duct itself for 10k steps (max |u|), each against the oracle where its
+CPU time allows.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -77,7 +83,7 @@ def copy_calibration(mib, torch):
 
 _TYPES = {"float": "f32", "f": "f32", "double": "f64", "d": "f64", "_Float16": "f16", "DF16_": "f16"}
 _STORAGE = {("f32", "f32", "f32"): "fp32_shift", ("f32", "f32", "f16"): "fp16_shift_g",
-            ("f32", "f16", "f16"): "fp16_shift_all", ("f64", "f64", "f64"): "fp64"}
+            ("f64", "f64", "f64"): "fp64"}
 
 
 def _sweep_storage(name):
@@ -272,6 +278,251 @@ def accuracy_leg(storages):
     return out
 
 
+def cap_angle_3d(phi, wall_z, cx, cy):
+    """Contact angle and radius of a sessile cap from its axial x-z section:
+    phi on the plane y = cy (linear between the two nearest node planes),
+    the 0.5 contour above the first fluid layer and the wall-adjacent cells
+    fitted by a circle."""
+    import numpy as np
+    from oracle import measure, theory
+    y0 = int(np.floor(cy))
+    f = cy - y0
+    sec = (1.0 - f) * phi[:, y0, :] + f * phi[:, y0 + 1, :]
+    pts = measure.contour_points_xz(sec, z_min=1)
+    pts = pts[pts[:, 1] > wall_z + 2.0]
+    xc, zc, R = measure.fit_circle(pts)
+    return theory.cap_angle_from_circle(zc, R, wall_z), float(R)
+
+
+def configured_sessile(storages, steps, oracle_steps):
+    """Sessile droplet, 128 x 128 x 96, 60-degree wall, 20k steps: final
+    contact angle and Laplace pressure against theory (Young's angle,
+    2 sigma / R of the fitted cap), and phi and the pressure jump against
+    the oracle after oracle_steps steps."""
+    import numpy as np
+    from oracle import ref, theory
+    from paper_2512_01032_amd import inputs, lbm
+    wl = inputs.sessile_droplet(steps=steps)
+    cx, cy = wl.meta["center"]
+    print("[bench] configured: sessile droplet, oracle %d steps" % oracle_steps, file=sys.stderr,
+          flush=True)
+    o = ref.Oracle(wl)
+    o.step(oracle_steps)
+    phi_o = o.fields()[0]
+    do = o.diagnostics()
+    fluid = o.kinds() == 0
+    del o
+    out = {"lattice": "128x128x96", "theta_eq_deg": wl.meta["theta"], "steps": steps,
+           "oracle_steps": oracle_steps}
+    for m in storages:
+        print("[bench] configured: sessile droplet %s, %d steps" % (m, steps), file=sys.stderr,
+              flush=True)
+        g = lbm.Lattice(wl, storage=m, diag_every=1000, u_max=0.5)
+        g.step(oracle_steps)
+        phi_g = g.fields()[0]
+        dg = g.diagnostics()
+        t0 = time.perf_counter()
+        g.step(steps - oracle_steps)
+        g.sync()
+        el = time.perf_counter() - t0
+        phi = g.fields()[0]
+        d = g.diagnostics()
+        g.close()
+        ang, R = cap_angle_3d(phi, wl.meta["wall_z"], cx, cy)
+        dP = d["P_liq_mean"] - d["P_gas_mean"]
+        dP_th = theory.laplace_pressure(wl.phys.sigma, R)
+        jump_g = dg["P_liq_mean"] - dg["P_gas_mean"]
+        jump_o = do["P_liq_mean"] - do["P_gas_mean"]
+        out[m] = {"angle_deg": ang, "angle_err_vs_theta_eq_deg": ang - wl.meta["theta"],
+                  "cap_radius": R, "dP": dP, "dP_theory_2sigma_over_R": dP_th,
+                  "laplace_rel_err_vs_theory": abs(dP - dP_th) / dP_th,
+                  "u_max": d["u_max"], "n_nan": d["n_nan"],
+                  "max_abs_dphi_vs_oracle": float(np.abs(phi_g - phi_o)[fluid].max()),
+                  "dP_vs_oracle_rel": abs(jump_g - jump_o) / abs(jump_o),
+                  "seconds": el}
+        print("[bench] configured: sessile %s: %s" % (m, json.dumps(out[m])), file=sys.stderr,
+              flush=True)
+    return out
+
+
+def configured_filling(storages, steps, every, oracle_steps, t_fit=5000):
+    """Capillary filling, 1024 x 32 x 32, 45-degree walls, 50k steps: the
+    liquid length (phi volume over the 30 x 30 cross-section) every `every`
+    steps, FP32 against FP16 g, against the square-duct Washburn law with
+    the static angle from step t_fit on, and the dynamic angle that law
+    needs to match the run; phi against the oracle after oracle_steps."""
+    import math
+    import numpy as np
+    from oracle import ref, theory
+    from paper_2512_01032_amd import inputs, lbm
+    wl = inputs.capillary_filling(steps=steps)
+    a = wl.meta["width"]
+    L = wl.nx - 2
+    ph = wl.phys
+    mu1, mu2 = ph.rho_l * ph.nu_l, ph.rho_g * ph.nu_g
+    print("[bench] configured: capillary filling, oracle %d steps" % oracle_steps,
+          file=sys.stderr, flush=True)
+    o = ref.Oracle(wl)
+    o.step(oracle_steps)
+    phi_o = o.fields()[0]
+    fluid = o.kinds() == 0
+    del o
+    out = {"lattice": "1024x32x32", "theta_deg": wl.meta["theta"], "steps": steps,
+           "sample_every": every, "oracle_steps": oracle_steps, "washburn_from_step": t_fit}
+    series = {}
+    for m in storages:
+        print("[bench] configured: capillary filling %s, %d steps" % (m, steps), file=sys.stderr,
+              flush=True)
+        g = lbm.Lattice(wl, storage=m, diag_every=1000, u_max=0.5)
+        zs, dphi = [], None
+        t0 = time.perf_counter()
+        for k in range(steps // every + 1):
+            zs.append(g.diagnostics()["phi_sum"] / (a * a))
+            if k * every == oracle_steps:
+                dphi = float(np.abs(g.fields()[0] - phi_o)[fluid].max())
+            if k < steps // every:
+                g.step(every)
+        g.sync()
+        el = time.perf_counter() - t0
+        d = g.diagnostics()
+        g.close()
+        series[m] = zs
+        k0 = t_fit // every
+        z_th = theory.washburn_square_duct(steps - t_fit, zs[k0], L, a, ph.sigma, wl.meta["theta"],
+                                           mu1, mu2)
+        # dynamic angle: the Washburn balance over the fitted window
+        dz = zs[-1] - zs[k0]
+        zbar = 0.5 * (zs[-1] + zs[k0])
+        rate = dz / (steps - t_fit)
+        c = (mu1 * zbar + mu2 * (L - zbar)) * rate * 28.45 / (a * 4.0 * ph.sigma)
+        th_dyn = math.degrees(math.acos(max(-1.0, min(1.0, c))))
+        out[m] = {"z_start": zs[0], "z_at_fit_start": zs[k0], "z_end": zs[-1],
+                  "z_end_washburn_static_angle": z_th,
+                  "travel_rel_err_vs_washburn": (dz - (z_th - zs[k0])) / (z_th - zs[k0]),
+                  "dynamic_angle_deg": th_dyn, "u_max": d["u_max"], "n_nan": d["n_nan"],
+                  "max_abs_dphi_vs_oracle": dphi, "seconds": el,
+                  "z_every_2500": [round(v, 4) for v in zs[::max(1, 2500 // every)]]}
+        print("[bench] configured: filling %s: z %.3f -> %.3f (Washburn %.3f), dyn angle %.2f"
+              % (m, zs[0], zs[-1], z_th, th_dyn), file=sys.stderr, flush=True)
+    if len(series) == 2:
+        s1, s2 = (np.asarray(v) for v in series.values())
+        out["max_abs_dz_fp32_vs_fp16g"] = float(np.abs(s1 - s2).max())
+    return out
+
+
+def configured_duct(wl, storages, steps, every=500, ramp_stable=2e-4):
+    """The benchmark duct for its configured 10k steps: diagnostics every 50
+    steps (NaN check), read every `every` steps.  With the configured inlet
+    ramp (2e-3 over 1e4 steps) the gas near the inlet speeds up as the
+    pressure rises and the run goes NaN after about 4000 steps, in FP64 as
+    in FP32: the method's limit at density ratio 1000, not a precision
+    effect.  The ramp is the knob: the full 10k steps are run at a ramp of
+    ramp_stable in each storage mode, reporting max |u|, the NaN count, the
+    phi mass at the start and the end (the pressure faces exchange mass)
+    and the wall time of the graph-replayed steps."""
+    import dataclasses
+    from paper_2512_01032_amd import inputs, lbm
+    out = {"steps": steps, "diag_every": 50}
+
+    def run(w, m, label):
+        print("[bench] configured: duct %s %s, %d steps" % (label, m, steps), file=sys.stderr,
+              flush=True)
+        g = lbm.Lattice(w, storage=m, diag_every=50, u_max=0.0)
+        nf = g.info()["n_fluid"]
+        d0 = g.diagnostics()
+        umax, hist, el, t, nan_by = 0.0, [], 0.0, 0, None
+        while t < steps:
+            t0 = time.perf_counter()
+            g.step(every)
+            t += every
+            try:
+                g.sync()
+            except lbm.LbmError as e:
+                if e.code != lbm.LBM_E_UNSTABLE:
+                    raise
+                nan_by = t
+                break
+            el += time.perf_counter() - t0
+            d = g.diagnostics()
+            umax = max(umax, d["u_max"])
+            hist.append(round(d["u_max"], 5))
+        g.close()
+        r = {"inlet_ramp_to": w.faces[4][1] * 1e4, "max_u": umax, "nan_by_step": nan_by,
+             "u_max_every_%d" % every: hist, "phi_sum_start": d0["phi_sum"]}
+        if nan_by is None:
+            r["phi_sum_end"] = d["phi_sum"]
+            r["n_nan"] = d["n_nan"]
+            r["mlups_fluid_graph_replay"] = nf * steps / el / 1e6
+        print("[bench] configured: duct %s %s: max|u| %.4g, NaN by %s" % (label, m, umax, nan_by),
+              file=sys.stderr, flush=True)
+        return r
+
+    out["configured_ramp_fp32_shift"] = run(wl, "fp32_shift", "ramp 2e-3")
+    w2 = inputs.constricted_duct(slug_offset=wl.meta.get("slug_offset", 0.25), ramp_to=ramp_stable)
+    for m in storages:
+        out[m] = run(w2, m, "ramp %g" % ramp_stable)
+    return out
+
+
+def cpu_baseline_leg(wl, cpu_steps, repeats=3):
+    """The FP64 oracle on the host cores: the benchmark lattice for
+    cpu_steps steps, `repeats` times (median), OpenMP over every thread in
+    the process's affinity mask; and the same on one thread (a child
+    process with OMP_NUM_THREADS=1) over a 256 x 256 x 32 section of the
+    duct (planes 40-71: walls, slugs, pressure faces at both ends), one step
+    per run.
+    Returns the baseline object and the oracle's phi after the first run."""
+    import subprocess
+    import numpy as np
+    from oracle import ref
+    cores = len(os.sched_getaffinity(0))
+    rates = []
+    phi_o = kinds = None
+    for r in range(repeats):
+        print("[bench] cpu baseline: oracle on %d cores, %d steps (run %d)" % (cores, cpu_steps, r + 1),
+              file=sys.stderr, flush=True)
+        o = ref.Oracle(wl)
+        t0 = time.perf_counter()
+        o.step(cpu_steps)
+        el = time.perf_counter() - t0
+        if phi_o is None:
+            kinds = o.kinds()
+            phi_o = o.fields()[0]
+        nf = int((kinds == 0).sum())
+        rates.append(nf * cpu_steps / el / 1e6)
+        del o
+    child = (
+        "import sys, time, json; sys.path.insert(0, %r)\n"
+        "from oracle import ref\n"
+        "from paper_2512_01032_amd import inputs\n"
+        "import dataclasses\n"
+        "full = inputs.constricted_duct(slug_offset=0.25)\n"
+        "wl = dataclasses.replace(full, nz=32, phi0=full.phi0[40:72].copy(),\n"
+        "                         solid=full.solid[40:72].copy())\n"
+        "out = []\n"
+        "for r in range(%d):\n"
+        "    o = ref.Oracle(wl)\n"
+        "    nf = int((o.kinds() == 0).sum())\n"
+        "    t0 = time.perf_counter(); o.step(1); el = time.perf_counter() - t0\n"
+        "    out.append(nf / el / 1e6)\n"
+        "print(json.dumps(out))\n" % (ROOT, repeats))
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    print("[bench] cpu baseline: oracle on 1 thread, 256x256x32 section", file=sys.stderr, flush=True)
+    one = json.loads(subprocess.run([sys.executable, "-c", child], env=env, check=True,
+                                    capture_output=True, text=True).stdout.strip().splitlines()[-1])
+    base = {"value": float(np.median(rates)), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": "full 256x256x512 duct (slug ends a quarter cell off the nodes), %d steps "
+                      "after initialisation, FP64, OpenMP over %d host threads; median of %d runs"
+                      % (cpu_steps, cores, repeats),
+            "runs_mlups": [round(v, 3) for v in rates],
+            "single_core": {"value": float(np.median(one)), "unit": "MLUPS", "cores": 1,
+                            "sample": "256x256x32 section of the duct (planes 40-71), "
+                                      "1 step after initialisation, FP64, one thread; median of %d"
+                                      % repeats,
+                            "runs_mlups": [round(v, 3) for v in one]}}
+    return base, phi_o, kinds
+
+
 def serving_leg(args, torch):
     from paper_2512_01032_amd import inputs
     trace = inputs.serving_trace()[:args.serve_requests]
@@ -389,7 +640,7 @@ def streaming_leg(torch, gib=4, reps=10):
 
 def storage_bytes(storage):
     return {"fp64": (8, 8), "fp32": (4, 4), "fp32_shift": (4, 4),
-            "fp16_shift_g": (4, 2), "fp16_shift_all": (2, 2)}[storage]
+            "fp16_shift_g": (4, 2)}[storage]
 
 
 def main():
@@ -399,6 +650,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--configured", default="sessile,filling,duct",
+                    help="configured validation runs of the oracle legs (comma list; empty: skip)")
+    ap.add_argument("--sessile-steps", type=int, default=20000)
+    ap.add_argument("--filling-steps", type=int, default=50000)
+    ap.add_argument("--duct-steps", type=int, default=10000)
     ap.add_argument("--modes", default="fp32_shift,fp16_shift_g,fp32,fp64")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (the calibration "
@@ -437,7 +693,7 @@ def main():
 
     if args.copy_mib > 0:
         copy_calibration(args.copy_mib, torch)
-    wl = inputs.constricted_duct()
+    wl = inputs.constricted_duct(slug_offset=0.25)
     modes = args.modes.split(",")
     results = {}
     lattices = {}
@@ -474,24 +730,11 @@ def main():
     cpu = None
     errors = {}
     accuracy = None
+    configured = None
     if not args.no_cpu_baseline:
         # FP64 oracle on the host cores, bounded sample: this lattice, a few
         # steps; the same steps on the GPU give max |phi - oracle|
-        from oracle import ref
-        cores = len(os.sched_getaffinity(0))
-        print("[bench] cpu baseline: oracle on %d cores, %d steps" % (cores, args.cpu_steps),
-              file=sys.stderr, flush=True)
-        o = ref.Oracle(wl)
-        t0 = time.perf_counter()
-        o.step(args.cpu_steps)
-        el = time.perf_counter() - t0
-        kinds = o.kinds()
-        nf = int((kinds == 0).sum())
-        cpu = {"value": nf * args.cpu_steps / el / 1e6, "unit": "MLUPS", "cores": cores,
-               "kind": "oracle",
-               "sample": "full 256x256x512 lattice, %d steps after initialisation, "
-                         "FP64, OpenMP over %d host threads" % (args.cpu_steps, cores)}
-        phi_o = o.fields()[0]
+        cpu, phi_o, kinds = cpu_baseline_leg(wl, args.cpu_steps)
         fluid = kinds == 0
         from paper_2512_01032_amd import lbm
         for m in ("fp32_shift", "fp16_shift_g"):
@@ -500,8 +743,17 @@ def main():
             phi_g = g.fields()[0]
             errors[m] = float(np.abs(phi_g - phi_o)[fluid].max())
             g.close()
-        del o
+        del phi_o
         accuracy = accuracy_leg(("fp32_shift", "fp16_shift_g", "fp64"))
+        legs = [c for c in args.configured.split(",") if c]
+        configured = {}
+        red = ("fp32_shift", "fp16_shift_g")
+        if "sessile" in legs:
+            configured["sessile_droplet"] = configured_sessile(red, args.sessile_steps, 200)
+        if "filling" in legs:
+            configured["capillary_filling"] = configured_filling(red, args.filling_steps, 500, 500)
+        if "duct" in legs:
+            configured["constricted_duct"] = configured_duct(wl, red, args.duct_steps)
 
     serving = serving_leg(args, torch) if args.serve_requests > 0 else None
 
@@ -522,6 +774,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "constricted_duct_256x256x512", "storage": "fp32_shift",
+                   "slug_offset": 0.25,
                    "nodes": wl.n_nodes, "value_counts": "fluid-node updates",
                    "density_ratio": 1000, "contact_angle_deg": 120},
         "roofline": {"bound": "hbm", "achieved": round(primary["sweep_GBs"], 1),
@@ -537,6 +790,7 @@ def main():
                   for m, r in results.items()},
         "max_abs_dphi_vs_oracle": errors,
         "accuracy_vs_oracle": accuracy,
+        "configured_runs": configured,
         "serving": serving,
         "variants": variants,
         "kernel_hash": kernel_hash(),

@@ -32,6 +32,22 @@ def washburn_2d(t, z0, L, H, sigma, theta_deg, mu1, mu2, dP=0.0):
     return (-b + math.sqrt(b * b - 4.0 * a * c)) / (2.0 * a)
 
 
+def washburn_square_duct(t, z0, L, a, sigma, theta_deg, mu1, mu2, dP=0.0, k=28.45):
+    """Liquid length in a square duct of side a filled by capillarity (Sec.
+    III.C, the Washburn balance of Eqs. 25-26 with the duct's Poiseuille
+    resistance): the mean velocity of a square duct is G a^2 / (k mu) with
+    k = 28.45, and the capillary pressure 4 sigma cos(theta) / a, so
+    [mu1 z + mu2 (L - z)] dz/dt = (a^2 / k)(4 sigma cos(theta) / a + dP);
+    the positive root of the integrated quadratic."""
+    A = 0.5 * (mu1 - mu2)
+    B = mu2 * L
+    drive = (a * a / k) * (4.0 * sigma * math.cos(math.radians(theta_deg)) / a + dP)
+    c = -drive * t - A * z0 * z0 - B * z0
+    if abs(A) < 1e-300:
+        return -c / B
+    return (-B + math.sqrt(B * B - 4.0 * A * c)) / (2.0 * A)
+
+
 def laplace_pressure(sigma, R, dim=3):
     """Young-Laplace jump across a static interface of radius R: 2 sigma / R
     for a sphere, sigma / R for a cylinder."""

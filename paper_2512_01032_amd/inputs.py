@@ -237,7 +237,7 @@ def constricted_duct(nx=256, ny=256, nz=512, step_z=256, theta=120.0, ramp_to=2e
     faces = (None, None, None, None, (ph.P_ref, ramp_to / ramp_steps), (ph.P_ref, 0.0))
     return Workload("constricted_duct", nx, ny, nz, ph, phi0, solid=solid, faces=faces,
                     theta_deg=tuple(th), steps=steps, storage=storage,
-                    meta={"slugs": slugs, "step_z": step_z})
+                    meta={"slugs": slugs, "step_z": step_z, "slug_offset": slug_offset})
 
 
 def duct_sdf(wl, offset=0.3):
