@@ -17,6 +17,24 @@ __global__ void __launch_bounds__(NTHREADS) advance_kernel(Desc* __restrict__ de
     if (step < D->stop_step) D->step = step + 1;
 }
 
+// The same over a list of descriptor slots (a batch whose other slots are
+// being filled or read back meanwhile on another stream: only the listed
+// descriptors are touched).
+__global__ void __launch_bounds__(NTHREADS) advance_list_kernel(Desc* __restrict__ descs,
+                                                                const int* __restrict__ slots, int n) {
+    const int k = blockIdx.x * NTHREADS + threadIdx.x;
+    if (k >= n) return;
+    Desc* D = descs + slots[k];
+    const int64_t step = D->step;
+    if (step < D->stop_step) D->step = step + 1;
+}
+
+hipError_t launch_advance_list(Desc* d, const int* slots, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    advance_list_kernel<<<dim3((n + NTHREADS - 1) / NTHREADS), dim3(NTHREADS), 0, s>>>(d, slots, n);
+    return hipGetLastError();
+}
+
 // Zero n doubles: read-back staging, whose nodes in dropped all-solid tiles
 // no read kernel writes.  A kernel rather than a memset node, so the call is
 // safe inside a captured stream as well.

@@ -208,6 +208,8 @@ hipError_t launch_restore(int storage, int qp, int parity, const Desc* d, const 
                           const double* pops, hipStream_t s);
 // step counter of every lattice in the table: t -> t+1 unless stopped
 hipError_t launch_advance(Desc* d, int nlat, hipStream_t s);
+// the same for the listed slots of a descriptor table only
+hipError_t launch_advance_list(Desc* d, const int* slots, int n, hipStream_t s);
 // p[0..n) = 0 (device memory)
 hipError_t launch_fill_zero(double* p, int64_t n, hipStream_t s);
 // after a sweep, before the step advances: equilibrium populations of every
