@@ -522,6 +522,53 @@ __device__ inline void g_out_pair(int i, const NodeState<T>& s, T rdif, T& vp, T
     vm = bm + T(0.5) * Km + filt;
 }
 
+// The post-collision pair of MODE_STEP with its terms grouped by their
+// parity in c_i: the function g_out_pair evaluates, with about half the
+// operations (in another order, so equal up to rounding).  With a = c_i.u,
+// b = c_i.grad, c = c_i.V, e = 9/2 a^2 - 3/2 u.u and r = rdif b + c, the pair
+// (i, opp(i)) is w_i (E +- O) with
+//   E = e A + 3/2 a r + C0 + om c_i c_i:Pi,   O = 3 a A + e r / 2 + c / 2,
+//   A = rho - (rdif u.grad + u.V) / 2,   C0 = pdev - u.V / 2 - om tr(Pi).
+// In scaled variables (a' = 3/2 a from u' = 3/2 u, e2 = e / 2,
+// b'' = c_i.(rdif grad), c'' = c_i.(V / 2), B = 2 A, r = b'' + 2 c''):
+//   E = e2 B + a' r + C0 + om c_i c_i:Pi,   O = a' B + e2 r + c''.
+// The rest population (c_0 = 0) is w_0 (e2 B + C0) with e2 = -3/4 u.u.
+template <typename T> struct PairPre {
+    T u15[3], rg[3], vh[3], k2, B, C0;
+};
+template <typename T>
+__device__ inline PairPre<T> pair_pre(const NodeState<T>& s, T rdif) {
+    PairPre<T> q;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        q.u15[k] = T(1.5) * s.u[k];
+        q.rg[k] = rdif * s.grad[k];
+        q.vh[k] = T(0.5) * s.V[k];
+    }
+    q.k2 = T(-0.75) * s.uu;
+    q.B = T(2) * s.rho - (rdif * s.ug + s.uV);
+    q.C0 = s.pdev - T(0.5) * s.uV - s.om * s.trPi;
+    return q;
+}
+template <typename T>
+__device__ inline T g_rest_step(const PairPre<T>& q) {
+    return T(wg(0)) * (q.k2 * q.B + q.C0);
+}
+template <typename T>
+__device__ inline void g_pair_step(int i, const NodeState<T>& s, const PairPre<T>& q, T& vp, T& vm) {
+    const T a = cdot(i, q.u15[0], q.u15[1], q.u15[2]);
+    const T b = cdot(i, q.rg[0], q.rg[1], q.rg[2]);
+    const T c = cdot(i, q.vh[0], q.vh[1], q.vh[2]);
+    const T e2 = a * a + q.k2;
+    const T r = T(2) * c + b;
+    const T E = e2 * q.B + (a * r + (s.om * ccpi(i, s.Pi) + q.C0));
+    const T O = a * q.B + (e2 * r + c);
+    const T w = T(wg(i));
+    const T wE = w * E, wO = w * O;
+    vp = wE + wO;
+    vm = wE - wO;
+}
+
 // Phase-field equilibrium deviation of the pair (i, opp(i)) (Eqs. 2-4):
 // h_eq_i - w_i href = w_i [(phi - href) + phi gam^h_i + theta c_i.n]
 template <typename T, int QP>
@@ -1050,16 +1097,19 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
             uw[2] = st.u[2] - nw[2] * un;
             slip = true;
         }
+        // waves without a node in the band skip the term (a uniform branch)
+        const bool wslip = __builtin_amdgcn_ballot_w64(slip) != 0u;
+        const T rho6 = T(6) * st.rho;
         auto mwall = [&](int i) -> T {
-            const T cuw = T(CX[i]) * uw[0] + T(CY[i]) * uw[1] + T(CZ[i]) * uw[2];
-            return T(6 * wg(i)) * st.rho * cuw;
+            return T(wg(i)) * (rho6 * cdot(i, uw[0], uw[1], uw[2]));
         };
         // write-back: half-way bounce-back at wall links through the slot
         // choice of put_pop (even: the own slot (x, ibar) anyway; odd: (x, ibar)
         // instead of the solid node's (x + c_i, i)), with the moving-wall term
         // applied in registers
         auto put_g = [&](int i, T v) {
-            if (MODE == MODE_STEP && !(SV && svx) && slip && i > 0 && ((solid >> i) & 1u)) v -= mwall(i);
+            if (MODE == MODE_STEP && !(SV && svx) && wslip)
+                if (slip && i > 0 && ((solid >> i) & 1u)) v -= mwall(i);
             const T vs = Store<SG>::scaled ? v * sg : v;
             if (MODE == MODE_STEP) put_pop<PAR>(gb, nb, solid, i, vs);
             else place_pop<PAR>(gb, nb, solid, i, vs);
@@ -1094,11 +1144,14 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
             const T x = hi ? gibar : s_fin[i - 1][tid] - m;
             return a * (gi - m) + (T(1) - a) * x;
         };
-        put_g(0, g_out<T, MODE>(0, st, rdif));
+        PairPre<T> pre;
+        if (MODE == MODE_STEP) pre = pair_pre(st, rdif);
+        put_g(0, MODE == MODE_STEP ? g_rest_step(pre) : g_out<T, MODE>(0, st, rdif));
 #pragma unroll
         for (int i = 1; i < QG; i += 2) {
             T vp, vm;
-            g_out_pair<T, MODE>(i, st, rdif, vp, vm);
+            if (MODE == MODE_STEP) g_pair_step(i, st, pre, vp, vm);
+            else g_out_pair<T, MODE>(i, st, rdif, vp, vm);
             if (svw) {
                 const bool si = (solid >> i) & 1u, sj = (solid >> (i + 1)) & 1u;
                 if (QREG) {

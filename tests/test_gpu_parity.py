@@ -687,22 +687,60 @@ def test_subvoxel_reduced_precision(storage, shape):
 
 
 # ------------------------------------------------------- capillary intrusion
+def _intrusion_length(wl, phi, fluid):
+    return float((np.clip(phi, 0.0, 1.0) * fluid).sum() / wl.meta["H"])
+
+
+def _oracle_g_rounding_spread(wl, steps, rel=1e-16, seeds=(1, 2, 3)):
+    """How far the FP64 oracle's liquid length moves when every step
+    multiplies each g population by (1 + rel u), u uniform in [-1, 1] (noise
+    of the size of FP64 rounding): the largest |z_noisy - z| over a few
+    seeds.  The conditioning of the run, which no FP64 evaluation that
+    rounds differently can beat."""
+    from oracle import ref
+    clean = ref.Oracle(wl)
+    clean.step(steps)
+    fluid = clean.kinds() == 0
+    z = _intrusion_length(wl, clean.fields()[0], fluid)
+    worst = 0.0
+    for sd in seeds:
+        o = ref.Oracle(wl)
+        rng = np.random.default_rng(sd)
+        for t in range(steps):
+            h, gp = o.pops()
+            o.set_pops(h, gp * (1.0 + rel * rng.uniform(-1.0, 1.0, gp.shape)), t)
+            o.step(1)
+        worst = max(worst, abs(_intrusion_length(wl, o.fields()[0], fluid) - z))
+    return worst
+
+
+@pytest.mark.timeout(600)
 @pytest.mark.parametrize("storage,frac", [("fp64", 1e-6), ("fp32_shift", 0.02), ("fp16_shift_g", 0.05)])
 def test_capillary_intrusion_matches_oracle(storage, frac):
     """Lucas-Washburn filling of a quasi-2D channel (the oracle pin's input):
     the liquid length after 12000 steps on the GPU against the FP64 oracle,
-    to a fraction of the distance the meniscus travelled (FP64: 1e-6; FP32
-    and FP16 g: the accumulated rounding of 12000 steps at a moving contact
-    line)."""
+    to a fraction of the distance the meniscus travelled (FP32 and FP16 g:
+    the accumulated rounding of 12000 steps at a moving contact line).  In
+    FP64 the run is conditioned by the mobility correction (Eq. 5): in the
+    nearly flat liquid next to the reservoir its sign term flips on rounding
+    noise, and the FP64 oracle fed per-step noise of the size of FP64
+    rounding in g moves the liquid length by 2e-5 to 8e-5 (3e-10 with the
+    correction off).  The FP64 bound is therefore max(1e-6 of the travel,
+    5 S), S that spread of the oracle over three noise seeds."""
     from paper_2512_01032_amd import inputs
     wl = inputs.channel_filling_2d(theta=45.0, nx=96, nz=10, fill=20, nu_l=0.03)
-    g, o = _run_pair(wl, 12000, storage)
+    steps = 12000
+    g, o = _run_pair(wl, steps, storage)
     fluid = o.kinds() == 0
-    H = wl.meta["H"]
-    z0 = float((np.clip(wl.phi0, 0.0, 1.0) * fluid).sum() / H)
-    zo = float((np.clip(o.fields()[0], 0.0, 1.0) * fluid).sum() / H)
-    zg = float((np.clip(g.fields()[0], 0.0, 1.0) * fluid).sum() / H)
+    z0 = _intrusion_length(wl, wl.phi0, fluid)
+    zo = _intrusion_length(wl, o.fields()[0], fluid)
+    zg = _intrusion_length(wl, g.fields()[0], fluid)
     print(storage, "z0 %.4f oracle %.6f gpu %.6f" % (z0, zo, zg), flush=True)
     g.close()
     assert zo - z0 > 5.0
-    assert abs(zg - zo) <= frac * (zo - z0)
+    limit = frac * (zo - z0)
+    if storage == "fp64":
+        spread = _oracle_g_rounding_spread(wl, steps)
+        limit = max(limit, 5.0 * spread)
+        print("oracle rounding spread", spread, "limit", limit, flush=True)
+    assert abs(zg - zo) <= limit, (zg - zo, limit)
