@@ -71,3 +71,29 @@ def cap_angle_from_circle(zc, R, z_wall):
     whose circle has centre height zc and radius R over a wall plane z_wall."""
     c = (z_wall - zc) / R
     return math.degrees(math.acos(max(-1.0, min(1.0, c))))
+
+
+def mixture_dynamic_viscosity(phi, rho_l, rho_g, nu_l, nu_g, mix_tanh, mix_phi=0.1, mix_width=0.001):
+    """Dynamic viscosity rho(phi) nu(phi) of the mixture: rho linear in the
+    clipped phi (Eq. 9), the relaxation time interpolated between the two
+    fluids' by F(phi) (Eqs. 10-12: F = phi; Sec. III.A: F = [tanh((phi -
+    mix_phi) / mix_width) + 1] / 2), nu = (tau - 1/2) / 3.  Works on arrays."""
+    import numpy as np
+    pb = np.clip(np.asarray(phi, dtype=float), 0.0, 1.0)
+    rho = rho_g + pb * (rho_l - rho_g)
+    F = 0.5 * (np.tanh((pb - mix_phi) / mix_width) + 1.0) if mix_tanh else pb
+    tau = (1.0 - F) * (3.0 * nu_g + 0.5) + F * (3.0 * nu_l + 0.5)
+    return rho * (tau - 0.5) / 3.0
+
+
+def poiseuille_intrusion_travel(t, M0, dmu, drive):
+    """Distance s travelled in time t by a liquid column in a plane channel
+    whose viscous resistance is sum over the channel of the dynamic
+    viscosity, M0 + dmu s (dmu = mu_liquid - mu_gas), driven by a pressure
+    drop p (per unit height squared over 12, drive = p H^2 / 12): the
+    positive root of dmu s^2 / 2 + M0 s = drive t (plane Poiseuille flow,
+    mean velocity = p H^2 / (12 mu L))."""
+    a = 0.5 * dmu
+    if abs(a) < 1e-300:
+        return drive * t / M0
+    return (-M0 + math.sqrt(M0 * M0 + 4.0 * a * drive * t)) / (2.0 * a)

@@ -168,11 +168,12 @@ def capillary_filling(nx=1024, ny=32, nz=32, fill=128, theta=45.0, steps=50000,
 
 
 def channel_filling_2d(nx=128, nz=18, fill=30, theta=45.0, ratio_mu=50.0, W=4.0, nu_l=0.01,
-                       storage="fp64"):
+                       storage="fp64", dP=0.0):
     """Quasi-2D capillary intrusion (y of width 1, periodic): plates at z = 0
     and z = nz - 1 (material 0, angle theta; channel height nz - 2 between the
-    half-way walls), pressure ghosts at P_ref at x = 0 (liquid reservoir side)
-    and x = nx - 1, liquid for x < fill; the optimised model."""
+    half-way walls), pressure ghosts at P_ref + dP at x = 0 (liquid reservoir
+    side) and at P_ref at x = nx - 1, liquid for x < fill; the optimised
+    model."""
     ph = optimised(Physics(W=W, nu_l=nu_l, nu_g=visc_ratio_nu_g(nu_l, 1.0, 0.001, ratio_mu)))
     x, y, z = _grid(nx, 1, nz)
     solid = np.zeros((nz, 1, nx), np.uint8)
@@ -180,7 +181,7 @@ def channel_filling_2d(nx=128, nz=18, fill=30, theta=45.0, ratio_mu=50.0, W=4.0,
     solid[nz - 1] = 1
     th = [90.0] * 16
     th[0] = theta
-    faces = ((ph.P_ref, 0.0), (ph.P_ref, 0.0), None, None, None, None)
+    faces = ((ph.P_ref + dP, 0.0), (ph.P_ref, 0.0), None, None, None, None)
     phi0 = tanh_profile(x - (fill - 0.5), W)
     return Workload("channel_filling_2d", nx, 1, nz, ph, phi0, solid=solid, faces=faces,
                     theta_deg=tuple(th), storage=storage,
