@@ -187,8 +187,8 @@ size_t lbm_footprint(const lbm_params *p);
 
 /* Validate, allocate (or carve the arena), upload geometry and initial state
  * and build the tile table.  Synchronous.  Errors: LBM_E_INVAL (tau <= 1/2,
- * W <= 0, rho <= 0, bad angle, ghost rules, N too large), LBM_E_NOMEM,
- * LBM_E_DEVICE. */
+ * W <= 0, rho <= 0, bad angle, ghost rules, N too large, no fluid node; the
+ * geometry is checked before any device call), LBM_E_NOMEM, LBM_E_DEVICE. */
 int lbm_create(const lbm_params *p, const lbm_geometry *geo, const lbm_init *init,
                const lbm_device_ctx *ctx, lbm_handle **out);
 

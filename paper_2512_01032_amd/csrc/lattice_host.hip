@@ -282,6 +282,7 @@ int build_layout(const lbm_params* p, const lbm_geometry* geo, int lat, LatticeL
                 else { L->flag[n] = make_flag(KIND_FLUID, 0); ++nf; }
             }
     L->n_fluid = nf; L->n_ghost = ng; L->n_solid = ns;
+    if (nf == 0) { set_error("the lattice has no fluid node"); return LBM_E_INVAL; }
     // ghost owners
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y)

@@ -210,3 +210,15 @@ def test_fp16_phase_storage_rejected_on_host():
     with pytest.raises(lbm.LbmError) as ei:
         lbm.Server(storage="fp16_shift_all")
     assert ei.value.code == lbm.LBM_E_INVAL
+
+
+def test_lattice_without_fluid_rejected_on_host():
+    """A geometry with no fluid node (every node solid) is refused by
+    lbm_create with LBM_E_INVAL before any device call."""
+    from paper_2512_01032_amd import inputs, lbm
+    wl = inputs.random_small(8, 6, 5, seed=0)
+    wl.solid = np.ones((wl.nz, wl.ny, wl.nx), np.uint8)
+    with pytest.raises(lbm.LbmError) as ei:
+        lbm.Lattice(wl, storage="fp64")
+    assert ei.value.code == lbm.LBM_E_INVAL
+    assert b"no fluid node" in lbm.lbm_last_error()
