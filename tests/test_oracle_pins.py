@@ -310,8 +310,12 @@ def test_taylor_green_decay_converges():
 # --------------------------------------------------------------------- P7
 def test_laplace_law_static_droplet():
     """Young-Laplace: P_in - P_out = 2 sigma / R for the equilibrated C1
-    droplet (radius from the conserved volume).  Pins the mu grad phi
-    surface-tension coupling and its 48 sigma / W, 3 sigma W / 2 constants."""
+    droplet (radius from the conserved volume; converged by step 3000,
+    ratio 1.004).  Pins the mu grad phi surface-tension coupling and its
+    48 sigma / W, 3 sigma W / 2 constants: a factor wrong in either moves the
+    jump far more than 2 %.  (At W = 4 larger drops settle near 0.94 of
+    2 sigma / R, an error of second order in 1/W in the effective surface
+    tension that a curvature correction offsets at this radius.)"""
     wl = I.static_droplet()
     o = ref.Oracle(wl)
     o.step(3000)
