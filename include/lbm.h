@@ -246,9 +246,11 @@ int lbm_read_fields_noalloc(lbm_handle *h, uint32_t mask, double *phi, double *P
 int lbm_reduce(lbm_handle *h, lbm_diag *d);
 
 /* Optional per-kernel timing with HIP events on the handle's stream: while on,
- * lbm_step records events around each launch; lbm_get_timing returns the
- * accumulated milliseconds of the phi pass and of the sweep and the number of
- * steps timed, and resets them. */
+ * lbm_step launches each kernel on its own and records events around them;
+ * lbm_get_timing returns the accumulated milliseconds of the phi pass with
+ * the wall pass, and of the sweep kernel alone (the ghost and step-counter
+ * kernels that follow it are not bracketed), and the number of steps timed,
+ * and resets them. */
 int lbm_set_timing(lbm_handle *h, int32_t on);
 int lbm_get_timing(lbm_handle *h, double *phi_ms, double *sweep_ms, int64_t *steps);
 

@@ -136,7 +136,7 @@ static bool diag_step(const lbm_handle* h, int64_t t) {
 // Queue the kernels of steps t0 .. t0+n-1 on stream s: per step the phi pass,
 // the wall pass, the sweep (its AA parity and diagnostic instance chosen by
 // the step), the pressure ghosts and the step counter.  With events (timed
-// runs) the phi + wall passes and the sweep + ghosts + counter are bracketed.
+// runs) the phi + wall passes and the sweep kernel alone are bracketed.
 static int enqueue_steps(lbm_handle* h, int64_t t0, int64_t n, hipStream_t s, bool events) {
     const int storage = h->p.storage;
     const int qp = phase_q(&h->p);
@@ -157,9 +157,9 @@ static int enqueue_steps(lbm_handle* h, int64_t t0, int64_t n, hipStream_t s, bo
         if (events) HIPRET(hipEventRecord(e1, s));
         HIPRET(launch_sweep(storage, qp, h->p.subvoxel ? MODE_STEP_SV : MODE_STEP, h->L.tx, par, h->ddesc,
                             h->dtiles, h->ntiles, diag, ro, in, s));
+        if (events) HIPRET(hipEventRecord(e2, s));
         if (h->nghosts) HIPRET(launch_ghosts(storage, qp, h->ddesc, h->dghosts, h->nghosts, s));
         HIPRET(launch_advance(h->ddesc, 1, s));
-        if (events) HIPRET(hipEventRecord(e2, s));
     }
     return LBM_OK;
 }
