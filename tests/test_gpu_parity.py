@@ -662,6 +662,23 @@ def test_subvoxel_walls_small_lattices_fp64(shape, kw, steps, q):
         assert err[k] <= FP64_TOL, (k, err[k])
 
 
+@pytest.mark.parametrize("mode,q", [(1, 7), (2, 19)])
+def test_subvoxel_walls_with_hysteresis_fp64(mode, q):
+    """Sub-voxel walls (f3) together with the contact-angle hysteresis blend
+    (f1, both readings) on both phase lattices: FP64 1e-10 after 14 steps."""
+    import dataclasses
+    from paper_2512_01032_amd import inputs
+    wl = inputs.random_small(40, 12, 10, seed=23, walls=True, subvoxel=True, open_x=True,
+                             optimised_model=True, u_amp=0.002)
+    wl.phys = dataclasses.replace(wl.phys, q_phase=q, hysteresis=mode, hyst_beta=0.95)
+    g, o = _run_pair(wl, 14)
+    err = compare_state(g, o, o.kinds())
+    print(mode, q, err, flush=True)
+    g.close()
+    for k in STRICT:
+        assert err[k] <= FP64_TOL, (k, err[k])
+
+
 def test_subvoxel_offset_plates_poiseuille_fp64():
     """Single-phase flow between plates offset by 0.3 (wall fractions 0.2 and
     0.8 on the two sides): 300 steps, FP64 1e-10 against the oracle."""
