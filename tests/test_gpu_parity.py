@@ -340,6 +340,33 @@ def test_full_size_fp64(name, steps):
     _check_fp64(g, o, name)
 
 
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("name,storage,bound", [("sessile", "fp32_shift", 1e-4), ("sessile", "fp16_shift_g", 1e-3),
+                                                ("filling", "fp32_shift", 1e-4), ("filling", "fp16_shift_g", 1e-3)])
+def test_full_size_reduced_precision(name, storage, bound):
+    """The sessile droplet and the capillary filling at full size in the
+    storage modes their configured runs use: max |phi - oracle| after 40
+    steps.  Both run the mobility correction next to walls, whose sign term
+    flips on rounding noise (R24): where the stated bound is exceeded, the
+    bound becomes 3 times the oracle's own spread under per-step noise of
+    the storage's size, as for the D3Q19 phase lattice."""
+    wl = _full(name)
+    g, o = _run_pair(wl, 40, storage)
+    fluid = o.kinds() == 0
+    dphi = float(np.abs(g.fields()[0] - o.fields()[0])[fluid].max())
+    g.close()
+    print(name, storage, "max |dphi|", dphi, flush=True)
+    limit = bound
+    if dphi > bound:
+        # one noise seed keeps the oracle work near a minute; a single seed
+        # can only under-state the spread, so the limit stays conservative
+        spread = _oracle_noise_spread(wl, 40, {"fp32_shift": 3e-8, "fp16_shift_g": 1e-6}[storage],
+                                      seeds=(2,), clean=o)
+        limit = max(bound, 3.0 * spread)
+        print("oracle noise spread", spread, "limit", limit, flush=True)
+    assert dphi <= limit, (dphi, limit)
+
+
 @pytest.mark.timeout(600)
 def test_full_size_filling_fp64_long_run_within_oracle_self_spread():
     """The capillary filling at full size (1024 x 32 x 32) in FP64 over 200
@@ -613,15 +640,17 @@ def test_d3q19_phase_restore_with_hysteresis_fp64():
         assert err[k] <= FP64_TOL, (k, err[k])
 
 
-def _oracle_noise_spread(wl, steps, amplitude, seeds=(2, 3, 4)):
+def _oracle_noise_spread(wl, steps, amplitude, seeds=(2, 3, 4), clean=None):
     """How far the FP64 oracle itself moves phi on this input when every
     step adds uniform noise of +-amplitude to the rest population h_0 of
     every fluid node: max over a few noise seeds of max |phi_noisy - phi|.
     The conditioning of the method on the input, which no evaluation in a
-    storage of that resolution can beat."""
+    storage of that resolution can beat.  `clean` may pass an oracle already
+    stepped `steps` times on `wl` without noise."""
     from oracle import ref
-    clean = ref.Oracle(wl)
-    clean.step(steps)
+    if clean is None:
+        clean = ref.Oracle(wl)
+        clean.step(steps)
     pc = clean.fields()[0]
     fluid = clean.kinds() == 0
     worst = 0.0
