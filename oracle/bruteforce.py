@@ -305,7 +305,7 @@ class BruteForce:
         if ph.interface_slip:
             band = (phi >= ph.slip_lo) & (phi <= ph.slip_hi)
         un = (self.nw * u).sum(0)
-        uw = (u - self.nw * un) * band
+        uw = getattr(ph, "slip_factor", 1.0) * (u - self.nw * un) * band
         hn = np.zeros_like(self.h)
         gn = np.zeros_like(self.g)
         for i in range(19):

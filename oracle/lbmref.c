@@ -20,8 +20,10 @@
  *       u and phi; Sec. III.A)
  *   S8  streaming (pull) with half-way bounce-back at solid links, or with
  *       sub-voxel walls the linearly interpolated bounce-back of g (h keeps
- *       the half-way rule); a ghost source hands over the populations S9 just
- *       set (Sec. III.A friction)
+ *       the half-way rule); in the slip band the wall moves with slip_factor
+ *       times the tangential fluid velocity (1: the free slip of Sec. III.A);
+ *       a ghost source hands over the populations S9 just set (Sec. III.A
+ *       friction)
  *   S10 swap lattices, t <- t+1
  * Equation numbers count every numbered display of the paper in order
  * (Eq. 1 the phase-field LB equation ... Eq. 19 the wall value phi_s,i).
@@ -590,14 +592,15 @@ static void one_step(lbmref_state *s) {
 #pragma omp parallel for schedule(static) if (s->N >= 16384)
     for (long y = 0; y < N; ++y) {
         if (s->kind[y] != K_FLUID) continue;
-        /* wall velocity seen by the slip bounce-back: tangential fluid velocity
-         * inside the interface band, zero elsewhere */
+        /* wall velocity seen by the slip bounce-back: the tangential fluid
+         * velocity times slip_factor inside the interface band (1: free
+         * slip), zero elsewhere */
         double uw[3] = {0.0, 0.0, 0.0};
         double ph = s->phi[y];
         if (p->interface_slip && ph >= p->slip_lo && ph <= p->slip_hi) {
             const double *nw = &s->nw[3 * y], *u = &s->u[3 * y];
             double un = nw[0] * u[0] + nw[1] * u[1] + nw[2] * u[2];
-            for (int a = 0; a < 3; ++a) uw[a] = u[a] - nw[a] * un;
+            for (int a = 0; a < 3; ++a) uw[a] = p->slip_factor * (u[a] - nw[a] * un);
         }
         for (int i = 0; i < 19; ++i) {
             long x = neighbour(s, y, i, -1);

@@ -71,6 +71,10 @@ typedef struct lbmref_params {
      * 1: the upstream node's post-collision value of the same step (the
      *    scheme as published); where that node is solid, the half-way rule. */
     int subvoxel_same_step;
+    /* wall velocity in the slip band, as a fraction of the tangential fluid
+     * velocity: 1 the free slip of Sec. III.A, 0 no slip, in between a
+     * partial slip (read only when interface_slip is set) */
+    double slip_factor;
 } lbmref_params;
 
 typedef struct lbmref_diag {

@@ -52,6 +52,7 @@ class Params(ctypes.Structure):
         ("hysteresis", ctypes.c_int), ("hyst_beta", ctypes.c_double),
         ("q_phase", ctypes.c_int),
         ("subvoxel_same_step", ctypes.c_int),
+        ("slip_factor", ctypes.c_double),
     ]
 
 
@@ -129,6 +130,7 @@ def make_params(wl, clamp_a=1e-12):
     p.hyst_beta = getattr(ph, "hyst_beta", 0.0)
     p.q_phase = int(getattr(ph, "q_phase", 7))
     p.subvoxel_same_step = int(getattr(wl, "meta", {}).get("subvoxel_same_step", False))
+    p.slip_factor = getattr(ph, "slip_factor", 1.0)
     return p
 
 

@@ -56,6 +56,9 @@ class Physics:
     interface_slip: bool = False    # Sec. III.A optimised model: free slip in the band
     slip_lo: float = 0.5
     slip_hi: float = 0.95
+    # wall velocity in the band as a fraction of the tangential fluid
+    # velocity: 1 the free slip of Sec. III.A, below 1 a partial slip
+    slip_factor: float = 1.0
     P_ref: float = T_G
     # Sec. III.A wall-value blend with the previous step: 0/False off; 1/True
     # with the blended value that step used; 2 with that step's own

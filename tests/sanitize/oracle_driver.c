@@ -21,6 +21,7 @@ static void base_params(lbmref_params *p, int nx, int ny, int nz) {
     p->mobility_corr = 1; p->gamma = -22.5; p->phi_M = 0.8; p->phi_m = 0.2; p->D = 1e-4;
     p->eps = 1e-10; p->mix_phi = 0.1; p->mix_width = 0.001; p->slip_lo = 0.5; p->slip_hi = 0.95;
     p->P_ref = 1.0 / 3.0; p->clamp_a = 1e-12; p->hyst_beta = 0.95; p->q_phase = 7;
+    p->slip_factor = 1.0;
     for (int k = 0; k < 16; ++k) p->theta_deg[k] = 90.0;
 }
 

@@ -37,7 +37,11 @@ def relmax(a, b):
                                        (dict(walls=True, open_x=True, optimised_model=True,
                                              subvoxel=True), 1, 19),
                                        (dict(walls=True, open_x=True, optimised_model=True,
-                                             subvoxel=True, same_step=True), False, 7)])
+                                             subvoxel=True, same_step=True), False, 7),
+                                       (dict(walls=True, open_x=True, optimised_model=True,
+                                             slip_factor=0.5), False, 7),
+                                       (dict(walls=True, open_x=True, optimised_model=True,
+                                             subvoxel=True, slip_factor=0.5), False, 7)])
 def test_bruteforce_reference_agrees(kw, hyst, q):
     """Whole-lattice NumPy transcription (np.roll streaming, masks) vs the
     node-by-node C oracle on a tiny lattice: pins indexing, periodic wrap,
@@ -45,8 +49,10 @@ def test_bruteforce_reference_agrees(kw, hyst, q):
     of the wall values, whose first blend only shows from the second step."""
     kw = dict(kw)
     same_step = kw.pop("same_step", False)
+    slip_factor = kw.pop("slip_factor", 1.0)
     wl = I.random_small(8, 6, 7, seed=3, **kw)
-    wl.phys = dataclasses.replace(wl.phys, hysteresis=hyst, hyst_beta=0.95, q_phase=q)
+    wl.phys = dataclasses.replace(wl.phys, hysteresis=hyst, hyst_beta=0.95, q_phase=q,
+                                  slip_factor=slip_factor)
     wl.meta["subvoxel_same_step"] = same_step
     o = ref.Oracle(wl)
     b = bruteforce.BruteForce(wl)
@@ -826,6 +832,76 @@ def test_interface_slip_band_gives_plug_flow(phi, plug):
     else:
         assert u[0] / centre <= 0.3
         assert u.mean() / (F * (t + 0.5) / rho) <= 0.5
+
+
+def _steady_channel_u(wl, chunk=5000, tol=1e-12, max_steps=60000):
+    """The oracle's steady velocity profile u_x(y) of a uniform channel
+    (stepped until one chunk changes it by less than tol relative)."""
+    o = ref.Oracle(wl)
+    ny = wl.ny
+    prev = None
+    for _ in range(max_steps // chunk):
+        o.step(chunk)
+        u = o.fields()[2][0, 0, 1:ny - 1, 0].copy()
+        if prev is not None and np.abs(u - prev).max() <= tol * np.abs(u).max():
+            return u
+        prev = u
+    raise AssertionError("no steady state in %d steps" % max_steps)
+
+
+@pytest.mark.parametrize("beta", [0.25, 0.5, 0.75])
+def test_partial_slip_shifts_the_no_slip_profile_by_the_wall_velocity(beta):
+    """Partial slip in the band (a variant of the Sec. III.A free slip): the
+    wall moves with beta times the tangential fluid velocity of the wall
+    node.  A wall moving with u_w under the moving-wall bounce-back has the
+    uniform flow u = u_w as an exact steady state, and the steady channel
+    flow is linear in the body force and the wall velocity, so the profile
+    is the no-slip one shifted by u_w: u(y) = u0(y) + u_w, and u_w = beta
+    u(1) closes to u_w = beta / (1 - beta) u0(1).  The no-slip profile u0
+    is the parabola whose curvature gives the mixture's viscosity (pinned by
+    the mixing-law test, checked again here at every beta).  A slip factor
+    applied twice or not at all, a wall velocity from the normal component
+    or a flipped sign of the moving-wall term moves u(1) by far more than
+    the 0.1 % allowed (the residue is the collision's cubic velocity
+    terms)."""
+    wl0, rho, F = _uniform_channel(0.7, slip=True)
+    wl0.phys = dataclasses.replace(wl0.phys, slip_factor=0.0)
+    u0 = _steady_channel_u(wl0)
+    wl, _, _ = _uniform_channel(0.7, slip=True)
+    wl.phys = dataclasses.replace(wl.phys, slip_factor=beta)
+    u = _steady_channel_u(wl)
+    pred = u0 + beta / (1.0 - beta) * u0[0]
+    assert np.abs(u - pred).max() <= 1e-3 * pred.max(), np.abs(u / pred - 1).max()
+    y = np.arange(1, wl.ny - 1, dtype=float)
+    nu_fit = -F / (2.0 * np.polyfit(y, u, 2)[0] * rho)
+    assert abs(nu_fit / 0.01 - 1.0) <= 0.01, nu_fit
+    # the wall velocity really is the fraction beta of the wall node's: the
+    # profile's value half-way to the wall exceeds the no-slip one's there
+    # by beta u(1)
+    c, c0 = np.polyfit(y, u, 2), np.polyfit(y, u0, 2)
+    assert abs((np.polyval(c, 0.5) - np.polyval(c0, 0.5)) / (beta * u[0]) - 1.0) <= 1e-3
+
+
+def test_slip_factor_zero_is_no_slip_and_one_is_free_slip_bitwise():
+    """The two ends of the partial-slip range are the friction models it
+    interpolates: factor 0 gives the no-slip walls bitwise (the wall
+    velocity is zero), factor 1 the free-slip band of Sec. III.A bitwise."""
+    base = I.random_small(12, 10, 9, seed=3, walls=True, open_x=True, optimised_model=True)
+    runs = {}
+    for key, slip, beta in (("noslip", False, 1.0), ("zero", True, 0.0), ("free", True, 1.0),
+                            ("free_default", True, None)):
+        wl = dataclasses.replace(base)
+        kw = {"interface_slip": slip}
+        if beta is not None:
+            kw["slip_factor"] = beta
+        wl.phys = dataclasses.replace(wl.phys, **kw)
+        o = ref.Oracle(wl)
+        o.step(20)
+        runs[key] = o.pops()
+    for a, b in (("noslip", "zero"), ("free", "free_default")):
+        for k in range(2):
+            assert np.array_equal(runs[a][k], runs[b][k]), (a, b, k)
+    assert not np.array_equal(runs["noslip"][1], runs["free"][1])
 
 
 # ------------------------------------------- sub-voxel walls, unsteady flow
