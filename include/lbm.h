@@ -15,7 +15,7 @@
  *   wetting at voxel walls: phi_s,i from the tanh profile along the rotated
  *                normal w                                      (Sec. II.B, Eqs. 17-19)
  *   friction: half-way bounce-back, free slip inside 0.5 <= phi <= 0.95 for
- *                the optimised model                            (Sec. III.A)
+ *                the optimised model, or a partial slip there   (Sec. III.A)
  *   pressure faces: Dirichlet P, Neumann u and phi              (Sec. III.A)
  *
  * Equation numbers count every numbered display of the paper in order.
@@ -68,7 +68,15 @@ enum lbm_storage {
 
 enum lbm_face_bc { LBM_BC_PERIODIC = 0, LBM_BC_PRESSURE = 1 };
 enum lbm_mix { LBM_MIX_LINEAR = 0, LBM_MIX_TANH = 1 };
-enum lbm_friction { LBM_FRICTION_NOSLIP = 0, LBM_FRICTION_INTERFACE_SLIP = 1 };
+/* friction at walls (Sec. III.A): half-way bounce-back (no slip) everywhere;
+ * or inside slip_lo <= phi <= slip_hi a moving-wall bounce-back whose wall
+ * velocity is the node's tangential fluid velocity (free slip, the optimised
+ * model) or slip_factor times it (partial slip, a variant between the two) */
+enum lbm_friction {
+    LBM_FRICTION_NOSLIP = 0,
+    LBM_FRICTION_INTERFACE_SLIP = 1,
+    LBM_FRICTION_PARTIAL_SLIP = 2
+};
 
 /* Problem statement (Sec. II, Sec. III.A).  All values in lattice units. */
 typedef struct lbm_params {
@@ -113,6 +121,10 @@ typedef struct lbm_params {
                                takes the linear interpolated bounce-back at each link's wall
                                fraction and the wall normal is the distance gradient; h keeps
                                the half-way rule (exact phi mass).  Other values: LBM_E_INVAL */
+    double slip_factor;     /* friction = LBM_FRICTION_PARTIAL_SLIP only: the wall velocity in
+                               the slip band as a fraction of the tangential fluid velocity,
+                               in [0, 1] (0: no slip, 1: the free slip); else LBM_E_INVAL.
+                               Ignored for the other friction models */
 } lbm_params;
 
 /* Geometry.  solid[n] = 0: fluid; 1 + k: solid of material k (< 16).

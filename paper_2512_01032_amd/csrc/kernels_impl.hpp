@@ -1086,8 +1086,9 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
         const T sg = ph[PI_SG];
         // D3Q19 write-back (AA slots of parity PAR)
         // free-slip band (Sec. III.A): at a wall link the wall moves with the
-        // tangential fluid velocity u_w, and the bounced-back population
-        // loses the moving-wall term 6 w_i rho (c_i . u_w)
+        // tangential fluid velocity u_w (times the slip factor for partial
+        // slip), and the bounced-back population loses the moving-wall term
+        // 6 w_i rho (c_i . u_w)
         T uw[3] = {T(0), T(0), T(0)};
         bool slip = false;
         if (MODE == MODE_STEP && solid && ph.friction && pc >= ph[PI_SLIP_LO] && pc <= ph[PI_SLIP_HI]) {
@@ -1099,7 +1100,7 @@ sweep_kernel(Desc* __restrict__ descs, const Tile* __restrict__ tiles, ReadOut r
         }
         // waves without a node in the band skip the term (a uniform branch)
         const bool wslip = __builtin_amdgcn_ballot_w64(slip) != 0u;
-        const T rho6 = T(6) * st.rho;
+        const T rho6 = ph[PI_SLIP_W6] * st.rho;   // 6 rho, times the slip factor
         auto mwall = [&](int i) -> T {
             return T(wg(i)) * (rho6 * cdot(i, uw[0], uw[1], uw[2]));
         };

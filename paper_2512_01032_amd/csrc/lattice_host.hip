@@ -109,8 +109,12 @@ int validate_params(const lbm_params* p, const lbm_geometry* geo) {
     if (p->mobility_corr && !(p->mc_D > 0)) { set_error("mobility correction needs D > 0"); return LBM_E_INVAL; }
     if (p->mix == LBM_MIX_TANH && !(p->mix_width > 0)) { set_error("mix_width must be > 0"); return LBM_E_INVAL; }
     if (p->mix != LBM_MIX_LINEAR && p->mix != LBM_MIX_TANH) { set_error("unknown mix %d", p->mix); return LBM_E_INVAL; }
-    if (p->friction != LBM_FRICTION_NOSLIP && p->friction != LBM_FRICTION_INTERFACE_SLIP) {
+    if (p->friction != LBM_FRICTION_NOSLIP && p->friction != LBM_FRICTION_INTERFACE_SLIP &&
+        p->friction != LBM_FRICTION_PARTIAL_SLIP) {
         set_error("unknown friction %d", p->friction); return LBM_E_INVAL;
+    }
+    if (p->friction == LBM_FRICTION_PARTIAL_SLIP && !(p->slip_factor >= 0.0 && p->slip_factor <= 1.0)) {
+        set_error("slip_factor %g outside [0, 1]", p->slip_factor); return LBM_E_INVAL;
     }
     const int dims[3] = {p->nx, p->ny, p->nz};
     for (int f = 0; f < 6; ++f) {
@@ -510,6 +514,9 @@ void fill_desc(const lbm_params* p, const lbm_geometry* geo, const LatticeLayout
     v[PI_PREF_DEV] = p->P_ref / TG - d->gref;
     v[PI_HBETA] = p->hysteresis ? p->hyst_beta : 0.0;
     v[PI_HBETA1] = 1.0 - v[PI_HBETA];
+    // moving-wall term of the slip band: 2 w_i rho (c_i . u_w) / T_g with
+    // u_w = slip_factor * tangential u, as w_i (6 slip_factor rho) (c_i . u_t)
+    v[PI_SLIP_W6] = 6.0 * (p->friction == LBM_FRICTION_PARTIAL_SLIP ? p->slip_factor : 1.0);
     for (int k = 0; k < PI_COUNT; ++k) {
         d->pd[k] = v[k];
         d->pf[k] = (float)v[k];

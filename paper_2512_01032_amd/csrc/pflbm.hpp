@@ -150,7 +150,7 @@ enum ParamIndex {
     PI_RHO_G = 0, PI_RDIF, PI_MU3, PI_MULAP, PI_TAU_G, PI_TAU_L, PI_THETA0, PI_MC_K, PI_MC_INVD,
     PI_MC_PHI_M, PI_MC_PHI_m, PI_EPS, PI_MIX_PHI, PI_MIX_INVW, PI_SLIP_LO, PI_SLIP_HI, PI_CLAMP_A,
     PI_HREF, PI_GREF, PI_SH, PI_SG, PI_INV_SH, PI_INV_SG, PI_ITAU_H, PI_FX, PI_FY, PI_FZ,
-    PI_K2W, PI_PREF_DEV, PI_HBETA, PI_HBETA1, PI_COUNT
+    PI_K2W, PI_PREF_DEV, PI_HBETA, PI_HBETA1, PI_SLIP_W6, PI_COUNT
 };
 static_assert(PI_COUNT <= 32, "parameter block");
 

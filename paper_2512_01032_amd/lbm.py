@@ -44,7 +44,7 @@ class lbm_params(ctypes.Structure):
         ("diag_every", c_int32), ("u_max", c_double),
         ("fp16_log2_scale_h", c_int32), ("fp16_log2_scale_g", c_int32),
         ("hysteresis", c_int32), ("hyst_beta", c_double), ("q_phase", c_int32),
-        ("subvoxel", c_int32),
+        ("subvoxel", c_int32), ("slip_factor", c_double),
     ]
 
 
@@ -181,8 +181,10 @@ def params_from_workload(wl, storage=None, diag_every=0, u_max=0.0):
     p.eps = ph.eps
     p.mix = 1 if ph.mix_tanh else 0
     p.mix_phi, p.mix_width = ph.mix_phi, ph.mix_width
-    p.friction = 1 if ph.interface_slip else 0
+    beta = float(getattr(ph, "slip_factor", 1.0))
+    p.friction = 0 if not ph.interface_slip else (1 if beta == 1.0 else 2)
     p.slip_lo, p.slip_hi = ph.slip_lo, ph.slip_hi
+    p.slip_factor = beta
     p.P_ref = ph.P_ref
     for f in range(6):
         fc = wl.faces[f]

@@ -15,6 +15,10 @@
 
 #include "lbm.h"
 
+/* friction model of the next cases */
+static int g_friction = LBM_FRICTION_INTERFACE_SLIP;
+static double g_slip_factor = 1.0;
+
 static void base(lbm_params *p, int nx, int ny, int nz) {
     memset(p, 0, sizeof(*p));
     p->nx = nx; p->ny = ny; p->nz = nz;
@@ -23,7 +27,7 @@ static void base(lbm_params *p, int nx, int ny, int nz) {
     p->sigma = 1e-3; p->W = 4.0; p->M = 1.0 / 6.0;
     p->mobility_corr = 1; p->mc_gamma = -22.5; p->mc_phi_M = 0.8; p->mc_phi_m = 0.2; p->mc_D = 1e-4;
     p->eps = 1e-10; p->mix = LBM_MIX_TANH; p->mix_phi = 0.1; p->mix_width = 0.001;
-    p->friction = LBM_FRICTION_INTERFACE_SLIP; p->slip_lo = 0.5; p->slip_hi = 0.95;
+    p->friction = g_friction; p->slip_factor = g_slip_factor; p->slip_lo = 0.5; p->slip_hi = 0.95;
     p->P_ref = 1.0 / 3.0; p->q_phase = 7; p->hyst_beta = 0.95;
 }
 
@@ -78,6 +82,12 @@ int main(void) {
     bad |= create_case("fp16_all", 20, 9, 7, 1, 0, 7, 0, 0, LBM_FP16_SHIFT_ALL, 1);
     bad |= create_case("bad_q", 20, 9, 7, 1, 0, 8, 0, 0, LBM_FP32_SHIFT, 1);
     bad |= create_case("empty", 0, 9, 7, 0, 0, 7, 0, 0, LBM_FP32_SHIFT, 1);
+    g_friction = LBM_FRICTION_PARTIAL_SLIP; g_slip_factor = 0.5;
+    bad |= create_case("partial_slip", 40, 12, 10, 1, 1, 7, 0, 1, LBM_FP32_SHIFT, 0);
+    g_slip_factor = 1.5;
+    bad |= create_case("bad_slip_factor", 40, 12, 10, 1, 1, 7, 0, 0, LBM_FP32_SHIFT, 1);
+    g_friction = 3; g_slip_factor = 0.5;
+    bad |= create_case("bad_friction", 40, 12, 10, 1, 1, 7, 0, 0, LBM_FP32_SHIFT, 1);
     printf(bad ? "FAIL\n" : "OK\n");
     return bad;
 }

@@ -48,10 +48,10 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(lbm_params), sizeof(lbm_geometry),
          sizeof(lbm_init), sizeof(lbm_device_ctx), sizeof(lbm_diag), sizeof(lbm_info),
          sizeof(lbm_server_cfg), sizeof(lbm_request), sizeof(lbm_result));
-  printf("%zu %zu %zu %zu %zu %zu\n", offsetof(lbm_params, face_bc),
+  printf("%zu %zu %zu %zu %zu %zu %zu\n", offsetof(lbm_params, face_bc),
          offsetof(lbm_params, diag_every), offsetof(lbm_params, fp16_log2_scale_g),
          offsetof(lbm_params, hysteresis), offsetof(lbm_params, hyst_beta),
-         offsetof(lbm_params, q_phase));
+         offsetof(lbm_params, q_phase), offsetof(lbm_params, slip_factor));
   return 0;
 }
 '''
@@ -69,7 +69,8 @@ int main(void) {
     offs = [int(v) for v in out[1].split()]
     assert offs == [lbm.lbm_params.face_bc.offset, lbm.lbm_params.diag_every.offset,
                     lbm.lbm_params.fp16_log2_scale_g.offset, lbm.lbm_params.hysteresis.offset,
-                    lbm.lbm_params.hyst_beta.offset, lbm.lbm_params.q_phase.offset]
+                    lbm.lbm_params.hyst_beta.offset, lbm.lbm_params.q_phase.offset,
+                    lbm.lbm_params.slip_factor.offset]
 
 
 @pytest.mark.parametrize("field,value", [("nu_l", 0.0), ("W", -1.0), ("rho_g", 0.0), ("nx", 0),
@@ -81,6 +82,21 @@ def test_invalid_parameters_rejected_on_host(field, value):
     wl = inputs.random_small(8, 6, 5, seed=0)
     p = lbm.params_from_workload(wl)
     setattr(p, field, value)
+    _create_is_rejected(wl, p)
+
+
+@pytest.mark.parametrize("friction,beta", [(3, 0.5), (-1, 0.5), (2, 1.5), (2, -0.1), (2, float("nan"))])
+def test_invalid_friction_rejected_on_host(friction, beta):
+    """An unknown friction model, or a partial-slip factor outside [0, 1]."""
+    from paper_2512_01032_amd import inputs, lbm
+    wl = inputs.random_small(8, 6, 5, seed=0, optimised_model=True)
+    p = lbm.params_from_workload(wl)
+    p.friction, p.slip_factor = friction, beta
+    _create_is_rejected(wl, p)
+
+
+def _create_is_rejected(wl, p):
+    from paper_2512_01032_amd import lbm
     assert lbm.lbm_footprint(ctypes.byref(p)) == 0
     with pytest.raises(lbm.LbmError) as ei:
         wl2 = wl

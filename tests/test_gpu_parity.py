@@ -811,6 +811,83 @@ def test_subvoxel_reduced_precision(storage, shape):
         assert err["phi"] <= 1e-3, err
 
 
+# ------------------------------------------------ partial slip (friction)
+@pytest.mark.parametrize("shape,kw,q,beta", [
+    ((8, 6, 7), dict(), 7, 0.5),
+    ((70, 13, 9), dict(), 7, 0.3),                              # several tiles, ragged
+    ((40, 12, 10), dict(subvoxel=True, u_amp=0.002), 7, 0.5),   # scaled by 1/(2q) there
+    ((40, 12, 10), dict(), 19, 0.75),                           # D3Q19 phase lattice
+    ((8, 6, 7), dict(), 7, 0.0),                                # the no-slip end
+])
+def test_partial_slip_fp64(shape, kw, q, beta):
+    """Partial slip in the interface band (the wall velocity a fraction beta
+    of the tangential fluid velocity) with walls of two materials and
+    pressure faces, optimised model: FP64 1e-10 after 12 steps.  The oracle
+    run at beta = 1 must differ, so the factor is exercised."""
+    import dataclasses
+    from oracle import ref
+    from paper_2512_01032_amd import inputs
+    wl = inputs.random_small(*shape, seed=31, walls=True, open_x=True, optimised_model=True, **kw)
+    wl.phys = dataclasses.replace(wl.phys, q_phase=q, slip_factor=beta)
+    g, o = _run_pair(wl, 12)
+    err = compare_state(g, o, o.kinds())
+    g.close()
+    print(shape, q, beta, err, flush=True)
+    for k in STRICT:
+        assert err[k] <= FP64_TOL, (k, err[k])
+    free = dataclasses.replace(wl, phys=dataclasses.replace(wl.phys, slip_factor=1.0))
+    of = ref.Oracle(free)
+    of.step(12)
+    assert np.abs(of.pops()[1] - o.pops()[1]).max() > 1e-9
+
+
+def test_partial_slip_channel_steady_fp64():
+    """A uniform mixture in the band between walls, driven by a body force,
+    with slip factor 0.5, run to its steady shifted parabola (20000 steps):
+    FP64 1e-10 against the oracle."""
+    import dataclasses
+    from paper_2512_01032_amd import inputs
+    ph = inputs.Physics(nu_l=0.01, nu_g=0.1, mobility_corr=False, mix_tanh=True,
+                        interface_slip=True, slip_factor=0.5, eps=1.0)
+    rho = ph.rho_g + 0.7 * (ph.rho_l - ph.rho_g)
+    ny = 12
+    ph = dataclasses.replace(ph, F_ex=(8.0 * rho * ph.nu_l * 0.01 / (ny - 2) ** 2, 0.0, 0.0))
+    solid = np.zeros((1, ny, 1), np.uint8)
+    solid[0, 0, 0] = solid[0, ny - 1, 0] = 1
+    wl = inputs.Workload("partial_slip_channel", 1, ny, 1, ph, np.full((1, ny, 1), 0.7),
+                         solid=solid)
+    g, o = _run_pair(wl, 20000)
+    err = compare_state(g, o, o.kinds())
+    ug = g.fields()[2][0, 0, 1:ny - 1, 0]
+    g.close()
+    print(err, ug, flush=True)
+    for k in STRICT:
+        assert err[k] <= FP64_TOL, (k, err[k])
+
+
+@pytest.mark.parametrize("storage", ["fp32_shift", "fp16_shift_g"])
+def test_partial_slip_reduced_precision(storage):
+    """FP32 arithmetic with partial slip at voxel and sub-voxel walls,
+    mobility correction off (R24 concerns the correction, not the walls):
+    phi, h, g, P within 1e-5 (FP32 shifted), phi 1e-3 (FP16 g) after 40
+    steps."""
+    import dataclasses
+    from paper_2512_01032_amd import inputs
+    for sv in (False, True):
+        wl = inputs.random_small(40, 12, 10, seed=33, walls=True, open_x=True, subvoxel=sv,
+                                 optimised_model=True, u_amp=0.002)
+        wl.phys = dataclasses.replace(wl.phys, mobility_corr=False, slip_factor=0.5)
+        g, o = _run_pair(wl, 40, storage)
+        err = compare_state(g, o, o.kinds())
+        g.close()
+        print(storage, sv, err, flush=True)
+        if storage == "fp32_shift":
+            for k in ("phi", "h", "g", "P"):
+                assert err[k] <= 1e-5, (k, err)
+        else:
+            assert err["phi"] <= 1e-3, err
+
+
 # ------------------------------------------------------- capillary intrusion
 def _intrusion_length(wl, phi, fluid):
     return float((np.clip(phi, 0.0, 1.0) * fluid).sum() / wl.meta["H"])

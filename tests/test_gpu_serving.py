@@ -165,6 +165,26 @@ def test_alone_equals_mix_bitwise_with_subvoxel_walls():
     _check_same(lbm, wls, res)
 
 
+def test_alone_equals_mix_bitwise_with_partial_slip():
+    """Lattices whose slip band uses different friction models (free slip,
+    partial slip at two factors, no slip) batched together: each lattice's
+    slip factor travels in its own constants, so every result is bitwise
+    the request run alone."""
+    import dataclasses
+    from paper_2512_01032_amd import inputs
+    lbm = _lbm()
+    wls = []
+    for k, (slip, beta) in enumerate(((True, 1.0), (True, 0.5), (True, 0.2), (False, 1.0))):
+        wl = inputs.random_small(40, 12, 10, seed=40 + k, walls=True, open_x=True,
+                                 optimised_model=True, u_amp=0.002, storage="fp32_shift")
+        wl.phys = dataclasses.replace(wl.phys, interface_slip=slip, slip_factor=beta)
+        wl.name += "_slip%g" % (beta if slip else 0.0)
+        wl.steps = 17
+        wls.append(wl)
+    res = _serve(lbm, wls, hbm_budget=1 << 30, use_graph=True, ticks_per_sync=6)
+    _check_same(lbm, wls, res)
+
+
 def test_alone_equals_mix_bitwise_with_hysteresis():
     """Lattices with contact-angle hysteresis (both readings) batched with
     plain ones: the wall pass over the concatenated near-wall lists updates
