@@ -579,8 +579,10 @@ def run_gpu(wl, storage, steps, warmup, torch):
 
 def variants_leg(wl, args, torch):
     """The method's options on the benchmark duct (FP32 shifted storage):
-    contact-angle hysteresis (Sec. III.A), the D3Q19 phase lattice, and
-    sub-voxel walls (every wall surface 0.3 cells into the fluid).  Each
+    contact-angle hysteresis (Sec. III.A), the D3Q19 phase lattice,
+    sub-voxel walls (every wall surface 0.3 cells into the fluid) and
+    partial slip in the interface band (wall velocity half the tangential
+    fluid velocity).  Each
     reports fluid MLUPS and the sweep against the HBM roofline with its own
     population bytes per node (the hysteresis history and the wall table
     are reported as extra bytes per near-wall node)."""
@@ -600,6 +602,8 @@ def variants_leg(wl, args, torch):
         elif name == "subvoxel":
             v.sdf = inputs.duct_sdf(wl, 0.3)
             extra = 21 * 4
+        elif name == "partial_slip":
+            v.phys = dataclasses.replace(wl.phys, slip_factor=0.5)
         else:
             raise SystemExit("unknown variant %s" % name)
         print("[bench] variant %s: 5 warmup + %d timed steps" % (name, args.variant_steps),
@@ -677,7 +681,7 @@ def main():
                          "(0 nodes: no cap)")
     ap.add_argument("--no-serve-baseline", action="store_true",
                     help="skip the one-at-a-time replay of the serving trace")
-    ap.add_argument("--variants", default="hysteresis,d3q19_phase,subvoxel",
+    ap.add_argument("--variants", default="hysteresis,d3q19_phase,subvoxel,partial_slip",
                     help="options of the method timed on the same duct in FP32 shifted storage "
                          "(comma list; empty: skip)")
     ap.add_argument("--variant-steps", type=int, default=60)

@@ -462,12 +462,13 @@ def test_full_size_duct_reduced_precision(duct_oracle, storage, bound):
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("variant", ["hysteresis", "d3q19_phase", "subvoxel"])
+@pytest.mark.parametrize("variant", ["hysteresis", "d3q19_phase", "subvoxel", "partial_slip"])
 def test_full_size_duct_variants_fp64(variant):
     """The method's options on the full benchmark duct, as the benchmark's
     variants leg runs them (hysteresis reading 1 with beta 0.95, the D3Q19
     phase lattice, every wall surface 0.3 cells into the fluid with
-    interpolated bounce-back): FP64 1e-10 against the oracle after 4 steps.
+    interpolated bounce-back, partial slip with factor 0.5): FP64 1e-10
+    against the oracle after 4 steps.
     The D3Q19 phase lattice in FP64 does not fit this lattice (a population
     group would exceed the 4 GiB of one buffer resource); it runs in FP32
     shifted storage, as the benchmark times it, held to max |phi - oracle|
@@ -481,6 +482,8 @@ def test_full_size_duct_variants_fp64(variant):
         wl.phys = dataclasses.replace(wl.phys, hysteresis=1, hyst_beta=0.95)
     elif variant == "d3q19_phase":
         wl.phys = dataclasses.replace(wl.phys, q_phase=19)
+    elif variant == "partial_slip":
+        wl.phys = dataclasses.replace(wl.phys, slip_factor=0.5)
     else:
         wl.sdf = inputs.duct_sdf(wl, 0.3)
     print("case duct %s %s, 4 steps" % (variant, "fp32_shift" if variant == "d3q19_phase" else "fp64"),
