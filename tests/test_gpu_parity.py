@@ -507,6 +507,65 @@ def test_full_size_duct_variants_fp64(variant):
     g.close()
 
 
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("storage,nz_max,period", [("fp32_shift", 630, 10), ("fp64", 630, 10),
+                                                   ("fp16_shift_g", 992, 16)])
+def test_maximum_size_lattice_equals_its_tiled_pattern(storage, nz_max, period):
+    """The largest lattice each storage mode accepts (256 x 256 x nz_max: a
+    population group of just under 4 GiB, addressed with 32-bit offsets; one
+    plane more is refused on the host), built by repeating a z-periodic
+    pattern 256 x 256 x period with walls, pressure faces and an obstacle:
+    after 6 steps every node's phi, P and u equal the same node of the
+    pattern run alone, bitwise (each node does the same arithmetic on the
+    same neighbourhood), so no offset up to the top of the group is wrong.
+    The pattern itself is held to the oracle (FP64 1e-10; FP32 shifted phi
+    1e-5 and FP16 g phi 1e-3 with the mobility correction off, R24)."""
+    import dataclasses
+    from oracle import ref
+    from paper_2512_01032_amd import inputs
+    lbm = _lbm()
+    small = inputs.random_small(256, 256, period, seed=51, walls=True, open_x=True,
+                                optimised_model=True, u_amp=0.002)
+    if storage != "fp64":
+        small.phys = dataclasses.replace(small.phys, mobility_corr=False)
+    k = nz_max // period
+    assert k * period == nz_max
+    big = dataclasses.replace(small, name="tiled_%d" % nz_max, nz=nz_max,
+                              phi0=np.tile(small.phi0, (k, 1, 1)),
+                              solid=np.tile(small.solid, (k, 1, 1)),
+                              u0=np.tile(small.u0, (1, k, 1, 1)),
+                              P0=np.tile(small.P0, (k, 1, 1)))
+    assert lbm.footprint(big, storage) > 0
+    assert lbm.footprint(dataclasses.replace(big, nz=nz_max + 1), storage) == 0
+    steps = 6
+    print("case maximum size %s 256x256x%d, pattern of %d planes, %d steps"
+          % (storage, nz_max, period, steps), flush=True)
+    gs = lbm.Lattice(small, storage=storage)
+    gs.step(steps)
+    fs = gs.fields()
+    gs.close()
+    gb = lbm.Lattice(big, storage=storage)
+    gb.step(steps)
+    fb = gb.fields()
+    gb.close()
+    print("big lattice stepped and read", flush=True)
+    for name, a, b in zip(("phi", "P", "u"), fs, fb):
+        if name == "u":
+            tiled = b.reshape(3, k, period, 256, 256)
+            same = all(np.array_equal(tiled[:, c], a) for c in range(k))
+        else:
+            tiled = b.reshape(k, period, 256, 256)
+            same = all(np.array_equal(tiled[c], a) for c in range(k))
+        assert same, name
+    del fb
+    o = ref.Oracle(small)
+    o.step(steps)
+    fluid = o.kinds() == 0
+    dphi = float(np.abs(fs[0] - o.fields()[0])[fluid].max())
+    print(storage, "pattern max |dphi|", dphi, flush=True)
+    assert dphi <= {"fp64": FP64_TOL, "fp32_shift": 1e-5, "fp16_shift_g": 1e-3}[storage]
+
+
 # ------------------------------------------------- contact-angle hysteresis
 def _hyst_workload(seed=8, mode=1):
     import dataclasses
