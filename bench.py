@@ -278,29 +278,13 @@ def accuracy_leg(storages):
     return out
 
 
-def cap_angle_3d(phi, wall_z, cx, cy):
-    """Contact angle and radius of a sessile cap from its axial x-z section:
-    phi on the plane y = cy (linear between the two nearest node planes),
-    the 0.5 contour above the first fluid layer and the wall-adjacent cells
-    fitted by a circle."""
-    import numpy as np
-    from oracle import measure, theory
-    y0 = int(np.floor(cy))
-    f = cy - y0
-    sec = (1.0 - f) * phi[:, y0, :] + f * phi[:, y0 + 1, :]
-    pts = measure.contour_points_xz(sec, z_min=1)
-    pts = pts[pts[:, 1] > wall_z + 2.0]
-    xc, zc, R = measure.fit_circle(pts)
-    return theory.cap_angle_from_circle(zc, R, wall_z), float(R)
-
-
 def configured_sessile(storages, steps, oracle_steps):
     """Sessile droplet, 128 x 128 x 96, 60-degree wall, 20k steps: final
     contact angle and Laplace pressure against theory (Young's angle,
     2 sigma / R of the fitted cap), and phi and the pressure jump against
     the oracle after oracle_steps steps."""
     import numpy as np
-    from oracle import ref, theory
+    from oracle import measure, ref, theory
     from paper_2512_01032_amd import inputs, lbm
     wl = inputs.sessile_droplet(steps=steps)
     cx, cy = wl.meta["center"]
@@ -336,7 +320,7 @@ def configured_sessile(storages, steps, oracle_steps):
         phi = g.fields()[0]
         d = g.diagnostics()
         g.close()
-        ang, R = cap_angle_3d(phi, wl.meta["wall_z"], cx, cy)
+        ang, R = measure.cap_angle_3d(phi, wl.meta["wall_z"], cx, cy)
         dP = d["P_liq_mean"] - d["P_gas_mean"]
         dP_th = theory.laplace_pressure(wl.phys.sigma, R)
         jump_g = dg["P_liq_mean"] - dg["P_gas_mean"]

@@ -42,3 +42,19 @@ def fit_circle(pts):
     xc, yc = sol[0] / 2.0, sol[1] / 2.0
     R = np.sqrt(sol[2] + xc * xc + yc * yc)
     return xc, yc, R
+
+
+def cap_angle_3d(phi, wall_z, cx, cy):
+    """Contact angle (degrees) and radius of a sessile cap on the wall plane
+    z = wall_z, from its axial x-z section: phi on the plane y = cy (linear
+    between the two nearest node planes), the 0.5 contour above the first
+    fluid layer and away from the wall-adjacent cells, fitted by a circle;
+    the angle is that of the circle meeting the wall plane."""
+    from oracle import theory
+    y0 = int(np.floor(cy))
+    f = cy - y0
+    sec = (1.0 - f) * phi[:, y0, :] + f * phi[:, y0 + 1, :]
+    pts = contour_points_xz(sec, z_min=1)
+    pts = pts[pts[:, 1] > wall_z + 2.0]
+    xc, zc, R = fit_circle(pts)
+    return theory.cap_angle_from_circle(zc, R, wall_z), float(R)
