@@ -28,7 +28,14 @@ from oracle import measure, ref  # noqa: E402
 from paper_2512_01032_amd import inputs  # noqa: E402
 
 
-def sessile(steps=20000, every=2000):
+def _dump(rec, out):
+    rec["generated_by"] = "tests/golden/make_configured_oracle_runs.py"
+    rec["omp_threads"] = os.environ.get("OMP_NUM_THREADS", "default")
+    with open(out, "w") as f:
+        json.dump(rec, f, indent=1)
+
+
+def sessile(out, steps=20000, every=2000):
     wl = inputs.sessile_droplet(steps=steps)
     cx, cy = wl.meta["center"]
     o = ref.Oracle(wl)
@@ -43,11 +50,13 @@ def sessile(steps=20000, every=2000):
                      "dP": d["P_liq_mean"] - d["P_gas_mean"], "phi_sum": d["phi_sum"]})
         print("sessile step %d: angle %.4f R %.4f dP %.6e (%.0f s)"
               % (t, ang, R, rows[-1]["dP"], time.time() - t0), flush=True)
-    return {"workload": "sessile droplet 128x128x96, 60-degree wall", "steps": steps,
-            "every": every, "wall_z": wl.meta["wall_z"], "center": [cx, cy], "series": rows}
+        # written at every checkpoint: a run cut short keeps what it reached
+        _dump({"workload": "sessile droplet 128x128x96, 60-degree wall", "steps": t,
+               "every": every, "wall_z": wl.meta["wall_z"], "center": [cx, cy],
+               "series": rows}, out)
 
 
-def filling(steps=10000, every=500):
+def filling(out, steps=10000, every=500):
     wl = inputs.capillary_filling()
     a = wl.meta["width"]
     o = ref.Oracle(wl)
@@ -57,8 +66,8 @@ def filling(steps=10000, every=500):
         o.step(every)
         zs.append(o.diagnostics()["phi_sum"] / (a * a))
         print("filling step %d: z %.5f (%.0f s)" % (t, zs[-1], time.time() - t0), flush=True)
-    return {"workload": "capillary filling 1024x32x32, 45-degree walls", "steps": steps,
-            "every": every, "width": a, "z": zs}
+        _dump({"workload": "capillary filling 1024x32x32, 45-degree walls", "steps": t,
+               "every": every, "width": a, "z": zs}, out)
 
 
 def main():
@@ -66,11 +75,7 @@ def main():
     out = sys.argv[2] if len(sys.argv) > 2 else os.path.join(
         HERE, {"sessile": "sessile_droplet_oracle.json",
                "filling": "capillary_filling_oracle.json"}[case])
-    rec = {"sessile": sessile, "filling": filling}[case]()
-    rec["generated_by"] = "tests/golden/make_configured_oracle_runs.py %s" % case
-    rec["omp_threads"] = os.environ.get("OMP_NUM_THREADS", "default")
-    with open(out, "w") as f:
-        json.dump(rec, f, indent=1)
+    {"sessile": sessile, "filling": filling}[case](out)
     print("wrote", out, flush=True)
 
 
