@@ -950,6 +950,43 @@ def test_partial_slip_reduced_precision(storage):
             assert err["phi"] <= 1e-3, err
 
 
+# ------------------------------------------ configured runs, oracle long runs
+def _golden(name):
+    import json
+    import os
+    return json.load(open(os.path.join(os.path.dirname(__file__), "golden", name)))
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("storage,bound", [("fp64", 1e-3), ("fp32_shift", 0.1),
+                                           ("fp16_shift_g", 0.1)])
+def test_configured_filling_follows_the_oracle_long_run(storage, bound):
+    """The capillary filling at its configured size (1024 x 32 x 32,
+    45-degree walls) over the first 10000 steps: the liquid length every 500
+    steps against the FP64 oracle's own run of the same 10000 steps
+    (tests/golden/capillary_filling_oracle.json, written by
+    make_configured_oracle_runs.py): within 1e-3 cells in FP64 (the run's
+    rounding sensitivity, R26, moves the intrusion by about 1e-4 of the
+    travel) and a tenth of a cell in FP32 shifted and FP16 g storage."""
+    from paper_2512_01032_amd import inputs
+    lbm = _lbm()
+    rec = _golden("capillary_filling_oracle.json")
+    wl = inputs.capillary_filling()
+    a = wl.meta["width"]
+    assert a == rec["width"]
+    print("case configured filling %s, %d steps" % (storage, rec["steps"]), flush=True)
+    g = lbm.Lattice(wl, storage=storage)
+    zs = [g.diagnostics()["phi_sum"] / (a * a)]
+    for _ in range(rec["steps"] // rec["every"]):
+        g.step(rec["every"])
+        zs.append(g.diagnostics()["phi_sum"] / (a * a))
+    g.close()
+    dz = np.abs(np.asarray(zs) - np.asarray(rec["z"]))
+    print(storage, "z", [round(v, 4) for v in zs[::4]], "max |dz|", float(dz.max()), flush=True)
+    assert len(zs) == len(rec["z"])
+    assert float(dz.max()) <= bound
+
+
 # ------------------------------------------------------- capillary intrusion
 def _intrusion_length(wl, phi, fluid):
     return float((np.clip(phi, 0.0, 1.0) * fluid).sum() / wl.meta["H"])
