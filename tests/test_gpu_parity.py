@@ -966,8 +966,9 @@ def test_configured_filling_follows_the_oracle_long_run(storage, bound):
     steps against the FP64 oracle's own run of the same 10000 steps
     (tests/golden/capillary_filling_oracle.json, written by
     make_configured_oracle_runs.py): within 1e-3 cells in FP64 (the run's
-    rounding sensitivity, R26, moves the intrusion by about 1e-4 of the
-    travel) and a tenth of a cell in FP32 shifted and FP16 g storage."""
+    rounding sensitivity, R26: the oracle itself started from populations
+    perturbed by 1e-15 relative ends 7e-5 to 3.0e-4 cells away over the
+    same steps) and a tenth of a cell in FP32 shifted and FP16 g storage."""
     from paper_2512_01032_amd import inputs
     lbm = _lbm()
     rec = _golden("capillary_filling_oracle.json")
