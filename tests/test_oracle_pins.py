@@ -996,3 +996,25 @@ def test_interface_width_2p5_is_unstable_at_density_ratio_1000(sigma):
     assert slab(2.5, 1000) >= 0.1
     assert slab(3.0, 3000) <= 1e-4
     assert slab(4.0, 3000) <= 1e-4
+
+
+# ------------------------------------------- stored long runs of the oracle
+def test_stored_filling_record_is_the_oracle_run():
+    """The stored long run of the capillary filling
+    (tests/golden/capillary_filling_oracle.json, written by
+    make_configured_oracle_runs.py) is the oracle's: its first two samples
+    are recomputed here (the initial fill and the liquid length after 500
+    steps), to 1e-9 cells (the phi-volume reduction's order depends on the
+    thread count)."""
+    import json
+    rec = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                      "capillary_filling_oracle.json")))
+    wl = I.capillary_filling()
+    a = wl.meta["width"]
+    assert rec["width"] == a and rec["every"] == 500
+    o = ref.Oracle(wl)
+    z0 = o.diagnostics()["phi_sum"] / (a * a)
+    o.step(500)
+    z1 = o.diagnostics()["phi_sum"] / (a * a)
+    assert abs(z0 - rec["z"][0]) <= 1e-9 and abs(z1 - rec["z"][1]) <= 1e-9, (z0, z1, rec["z"][:2])
+
