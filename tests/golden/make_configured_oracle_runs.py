@@ -8,11 +8,13 @@ workloads, the references the GPU's long runs are compared with:
   capillary_filling_oracle.json the capillary filling (1024 x 32 x 32,
       45-degree walls, Sec. III.C) over its first 10000 steps: every 500
       steps the liquid length (phi volume over the channel cross-section).
+  capillary_filling_oracle_50000.json the same over the configured 50000
+      steps (filling 50000).
 
 It calls only the oracle, its measurement helpers and the seeded input
 generators.  Usage (the default output is this folder):
 
-  python tests/golden/make_configured_oracle_runs.py sessile|filling [OUT.json]
+  python tests/golden/make_configured_oracle_runs.py sessile|filling [STEPS] [OUT.json]
 """
 from __future__ import annotations
 
@@ -72,10 +74,13 @@ def filling(out, steps=10000, every=500):
 
 def main():
     case = sys.argv[1]
-    out = sys.argv[2] if len(sys.argv) > 2 else os.path.join(
-        HERE, {"sessile": "sessile_droplet_oracle.json",
-               "filling": "capillary_filling_oracle.json"}[case])
-    {"sessile": sessile, "filling": filling}[case](out)
+    steps = int(sys.argv[2]) if len(sys.argv) > 2 else {"sessile": 20000, "filling": 10000}[case]
+    default = {"sessile": "sessile_droplet_oracle.json",
+               "filling": "capillary_filling_oracle.json"}[case]
+    if case == "filling" and steps != 10000:
+        default = "capillary_filling_oracle_%d.json" % steps
+    out = sys.argv[3] if len(sys.argv) > 3 else os.path.join(HERE, default)
+    {"sessile": sessile, "filling": filling}[case](out, steps=steps)
     print("wrote", out, flush=True)
 
 
