@@ -1018,3 +1018,17 @@ def test_stored_filling_record_is_the_oracle_run():
     z1 = o.diagnostics()["phi_sum"] / (a * a)
     assert abs(z0 - rec["z"][0]) <= 1e-9 and abs(z1 - rec["z"][1]) <= 1e-9, (z0, z1, rec["z"][:2])
 
+
+def test_stored_filling_records_agree():
+    """The two stored oracle runs of the capillary filling (10000 steps on
+    16 host threads, 50000 steps on 8) give the same liquid length at every
+    sample they share, to 1e-9 cells (only the phi-volume reduction's order
+    differs between them)."""
+    import json
+    g = os.path.join(os.path.dirname(__file__), "golden")
+    a = json.load(open(os.path.join(g, "capillary_filling_oracle.json")))
+    b = json.load(open(os.path.join(g, "capillary_filling_oracle_50000.json")))
+    assert a["every"] == b["every"] and b["steps"] == 50000 and len(b["z"]) == 101
+    k = len(a["z"])
+    assert np.abs(np.asarray(a["z"]) - np.asarray(b["z"][:k])).max() <= 1e-9
+
